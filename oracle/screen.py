@@ -172,7 +172,9 @@ def masked_average(vis, flags, M: int, F: int = 1):
     keep = (np.asarray(flags) == 0)                          # [..., C/F, T/M]
     keep = np.repeat(np.repeat(keep, F, axis=-2), M, axis=-1)  # [..., C, T]
     n = keep.sum(axis=-1)
-    total = (v * keep[..., None]).sum(axis=-2)
+    # flagged samples are left out of the sum (not multiplied by zero: a NaN or
+    # Inf in a flagged window must not reach the average)
+    total = np.where(keep[..., None], v, 0.0).sum(axis=-2)
     with np.errstate(invalid="ignore", divide="ignore"):
         avg = np.where(n[..., None] > 0, total / np.maximum(n, 1)[..., None], 0.0)
     return avg, n / T

@@ -312,12 +312,16 @@ def test_flag_options_clear_tests():
 
 
 def test_nonfinite_input_flags_window():
+    """A NaN / Inf sample flags its window, and the excluded window leaves the average
+    equal to the plain mean of the other window (numpy.mean)."""
     rng = np.random.default_rng(20)
-    vis = _cn(rng, (1, 1, 32, 4))
-    vis[0, 0, 5, 1] = np.nan
-    out = oracle.screen(vis, Params(M=16))
-    assert out["flags"][0, 0, 0] & SK_LOW and out["flags"][0, 0, 0] & DS_RE
-    assert np.isfinite(out["avg"]).all()
+    for bad in (np.nan, np.inf):
+        vis = _cn(rng, (1, 1, 32, 4))
+        vis[0, 0, 5, 1] = bad
+        out = oracle.screen(vis, Params(M=16, s_low=-1e30, s_high=1e30, gamma=1.0))
+        assert out["flags"][0, 0, 0] != 0 and out["flags"][0, 0, 1] == 0
+        np.testing.assert_allclose(out["avg"][0, 0], vis[0, 0, 16:].mean(axis=0), rtol=1e-13)
+        assert out["weight"][0, 0] == 0.5
 
 
 def test_all_zero_window_is_flagged_low():
