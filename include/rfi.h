@@ -1,0 +1,170 @@
+/*
+ * rfi.h -- C ABI of librfi, an MI355X (gfx950) implementation of the online,
+ * post-correlation RFI screen of Yatawatta, Boonstra & Broekema, "Energy and
+ * polarization based online interference mitigation in radio interferometry"
+ * (arXiv 2412.14775).
+ *
+ * Problem statement (Section 2): N dual-polarised receivers give N(N+1)/2
+ * baseline streams (autocorrelations included).  Each stream carries, per
+ * channel and time sample i, the 2x2 correlation matrix
+ *     V_i = [[xx_i, xy_i], [yx_i, yy_i]]                       (Section 2, eq. V)
+ * and every stream is screened separately.  For each window of W samples the
+ * screen forms complex Stokes I = xx+yy, Q = xx-yy, U = xy+yx, V = j(xy-yx)
+ * (eq. IQUV), the spectral-kurtosis statistic of |I| (Section 2.1, Table 1)
+ * and the directional statistic of the real and the imaginary parts of
+ * (Q, U, V) (Section 2.2, Table 2), flags the window when a statistic leaves
+ * its range (the tests are ORed), and leaves flagged windows out of the time
+ * average, whose weight is updated (Section 2.1).
+ *
+ * Conventions for every entry point
+ *  - Pointers named as device pointers must be device memory on the plan's
+ *    device (HIP/PyTorch allocations); the caller owns every I/O buffer.
+ *  - Functions return RFI_OK (0) or a negative rfi_status.  On error a message
+ *    is available from rfi_last_error() (thread-local) and no output is
+ *    written.  Invalid arguments are rejected before any device call.
+ *  - No C++ exception crosses this boundary.
+ *  - rfi_screen is asynchronous: it enqueues kernels on the caller's HIP
+ *    stream and returns; the caller synchronises before reading outputs.
+ */
+#ifndef RFI_H
+#define RFI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RFI_ABI_VERSION 1
+
+typedef enum rfi_status {
+  RFI_OK = 0,
+  RFI_ERR_INVALID_ARGUMENT = -1, /* bad shape, threshold, pointer or alignment          */
+  RFI_ERR_OUT_OF_MEMORY = -2,    /* device allocation failed                             */
+  RFI_ERR_DEVICE = -3,           /* a HIP call failed; the message holds HIP's error     */
+  RFI_ERR_UNSUPPORTED = -4       /* valid request this build does not implement          */
+} rfi_status;
+
+/* Storage format of the visibilities.  Arithmetic is FP32 for both. */
+typedef enum rfi_vis_format {
+  RFI_VIS_CF32 = 0, /* complex64: per sample 4 x (re, im) float32, 32 bytes        */
+  RFI_VIS_CF16 = 1  /* complex half: per sample 4 x (re, im) float16, 16 bytes     */
+} rfi_vis_format;
+
+/* Option bits of rfi_params.options. */
+enum {
+  RFI_OPT_NO_SK = 1u,   /* do not apply the spectral-kurtosis test (bits 0-1 cleared)  */
+  RFI_OPT_NO_DS = 2u,   /* do not apply the directional test (bits 2-3 cleared)        */
+  RFI_OPT_ADAPTIVE = 4u /* per-stream thresholds from running null statistics, below    */
+};
+
+/* Flag bits written per window.  A window is flagged when any bit is set. */
+enum {
+  RFI_FLAG_SK_LOW = 1u,  /* not (tau >= s_low)      Section 2.1                  */
+  RFI_FLAG_SK_HIGH = 2u, /* tau > s_high            Section 2.1                  */
+  RFI_FLAG_DS_RE = 4u,   /* not (r_re <= gamma)     Section 2.2, real parts      */
+  RFI_FLAG_DS_IM = 8u    /* not (r_im <= gamma)     Section 2.2, imaginary parts */
+};
+
+/*
+ * Screen parameters: the problem statement of Section 2 and the
+ * hyperparameters of Section 2.3 (d, s_low, s_high, gamma, W), fixed a priori.
+ */
+typedef struct rfi_params {
+  int32_t n_stations;  /* N >= 1                                                          */
+  int32_t n_baselines; /* must equal N(N+1)/2: pairs (p,q), p <= q, row-major upper triangle */
+  int32_t n_channels;  /* C >= 1                                                          */
+  int32_t n_samples;   /* T, time samples per integration; T % block_m == 0               */
+  int32_t block_m;     /* M, window length in time samples (the paper's W when F = 1), >= 2 */
+  int32_t vis_format;  /* rfi_vis_format                                                  */
+  float sk_d;          /* d > 0 (Section 2.1)                                              */
+  float sk_low;        /* s_low < s_high (Section 2.1)                                     */
+  float sk_high;
+  float ds_gamma;      /* gamma in [0, 1] (Section 2.2)                                    */
+  float eps;           /* epsilon of Tables 1-2 (S1^2 + eps, sqrt(.) + eps); >= 0, finite  */
+  uint32_t options;    /* RFI_OPT_* bits                                                   */
+  float kappa_sk;      /* ADAPTIVE: s_low/high = mean_tau -/+ kappa_sk * sd_tau, kappa >= 0 */
+  float kappa_ds;      /* ADAPTIVE: gamma_re/im = mean_r + kappa_ds * sd_r                  */
+  int32_t n_warm;      /* ADAPTIVE: windows a stream must have seen before its own thresholds */
+  int32_t block_f;     /* F, channels per window (time x frequency window); 1 = time only  */
+} rfi_params;
+
+typedef struct rfi_plan rfi_plan; /* opaque */
+
+/* Fill *p with defaults: eps = 2^-23, d = 1, s_low = 0.5, s_high = 2, gamma = 0.4,
+ * block_f = 1, kappa_sk = kappa_ds = 3, n_warm = 0, CF32, options 0; sizes zero. */
+void rfi_params_default(rfi_params *p);
+
+/*
+ * Validate *params, choose the kernel for (vis_format, block_m), and allocate
+ * the plan's device state on `device` (the ADAPTIVE state, zeroed; nothing
+ * otherwise).  On success *out receives the plan; on error *out is NULL.
+ * Errors: INVALID_ARGUMENT (shape or threshold rules above), DEVICE, OUT_OF_MEMORY.
+ */
+int rfi_plan_create(const rfi_params *params, int device, rfi_plan **out);
+
+/*
+ * Screen one integration (Sections 2.1-2.2).  All pointers are device pointers.
+ *   vis    [B][C][T][4] samples in the plan's format, pol order (xx, xy, yx, yy),
+ *          (re, im) interleaved; 16-byte aligned.                       (read)
+ *   avg    [B][C][4][2] float32: flag-masked time average of each correlation
+ *          over unflagged samples; 0 when every window is flagged.       (write)
+ *   weight [B][C] float32: unflagged fraction of the T samples.           (write)
+ *   flags  [B][C][T/M] uint8 RFI_FLAG_* bits per window, or NULL.         (write)
+ *   stats  [B][C][T/M][3] float32 (tau, r_re, r_im) per window, or NULL.  (write)
+ *   hip_stream: a hipStream_t (NULL = default stream).
+ * With RFI_OPT_ADAPTIVE the thresholds of each stream come from the plan's
+ * state, which this call then updates from the unflagged windows; calls on one
+ * plan must therefore be ordered (one stream at a time).  Buffers must not alias.
+ * Asynchronous; errors: INVALID_ARGUMENT (NULL or misaligned pointer), DEVICE.
+ */
+int rfi_screen(rfi_plan *plan, const void *vis, float *avg, float *weight, uint8_t *flags,
+               float *stats, void *hip_stream);
+
+/* Free the plan and its device state.  NULL-safe.  Waits for nothing: the caller
+ * must not destroy a plan with work in flight. */
+int rfi_destroy(rfi_plan *plan);
+
+/* Message of the last failed call on this thread ("" if none).  Valid until the
+ * next call on this thread. */
+const char *rfi_last_error(void);
+
+/*
+ * Device bytes one rfi_screen call of this plan touches or owns: the plan's
+ * own state plus vis, avg, weight and flags (stats excluded).  Used for
+ * admission control by memory footprint.
+ */
+int rfi_plan_footprint(const rfi_plan *plan, size_t *bytes);
+
+/*
+ * ADAPTIVE state, per stream b*C + c, 32 bytes:
+ *   uint32 n; float mean[3]; float m2[3]; uint32 reserved
+ * (statistics in the order tau, r_re, r_im; m2 = sum of squared deviations).
+ * rfi_state_get / rfi_state_set copy the whole state to / from host memory
+ * synchronously (checkpoint / resume); bytes must equal rfi_state_bytes().
+ * rfi_state_reset zeroes it on the given stream.
+ */
+size_t rfi_state_bytes(const rfi_plan *plan);
+int rfi_state_get(rfi_plan *plan, void *host_dst, size_t bytes);
+int rfi_state_set(rfi_plan *plan, const void *host_src, size_t bytes);
+int rfi_state_reset(rfi_plan *plan, void *hip_stream);
+
+/*
+ * Read-only streaming probe: reads `bytes` (multiple of 16) from device buffer
+ * `src` once and writes one float per workgroup into `sink` (device, at least
+ * rfi_probe_sink_floats(bytes) floats) so the reads cannot be elided.
+ * Gives the achievable HBM read bandwidth that bounds rfi_screen.
+ */
+size_t rfi_probe_sink_floats(size_t bytes);
+int rfi_probe_read(const void *src, size_t bytes, float *sink, void *hip_stream);
+
+/* Plain device copy of `bytes` (multiple of 16): a kernel of known traffic used to
+ * calibrate hardware byte counters. */
+int rfi_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RFI_H */

@@ -1,0 +1,62 @@
+// Internal declarations shared by the C-ABI layer (api.hip) and the kernels
+// (screen.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rfi {
+
+// Launch arguments of the screen kernels (passed by value as the kernel argument).
+struct ScreenArgs {
+  const uint8_t *vis;   // [streams][T] samples of `sample_bytes` each
+  float *avg;           // [streams][8]
+  float *weight;        // [streams]
+  uint8_t *flags;       // [streams][nW] or null
+  float *stats;         // [streams][nW][3] or null
+  uint32_t *state;      // [streams][8] adaptive state or null
+  int64_t n_streams;    // B * C
+  int32_t T;            // samples per stream
+  int32_t M;            // window length
+  int32_t nW;           // windows per stream = T / M
+  int32_t n_seg;        // waves per stream (1, 2 or 4)
+  int32_t seg_samples;  // samples per wave segment = T / n_seg
+  int32_t seg_windows;  // windows per wave segment = seg_samples / M
+  float pre;            // (M d + 1) / (M - 1)
+  float Mf;             // M as float
+  float invM;           // 1 / M
+  float eps;
+  float s_low, s_high, gamma;
+  float kappa_sk, kappa_ds;
+  int32_t n_warm;
+  uint32_t options;
+  float invT;
+};
+
+// Adaptive state record, one per stream (32 bytes; layout is part of the ABI).
+struct StateRec {
+  uint32_t n;
+  float mean[3];
+  float m2[3];
+  uint32_t reserved;
+};
+static_assert(sizeof(StateRec) == 32, "state record is 32 bytes");
+
+enum : int { FMT_CF32 = 0, FMT_CF16 = 1 };
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kMaxTiledLog2M = 12;  // tiled kernels exist for M = 2 .. 4096
+
+// Kernel selection.  Returns hipErrorInvalidValue when no kernel matches.
+hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream);
+// Samples per lane per iteration of the tiled kernel for a format (4 for CF32, 8 for CF16).
+int tiled_samples_per_lane(int fmt);
+bool tiled_supports(int M);
+
+hipError_t launch_probe_read(const void *src, size_t bytes, float *sink, hipStream_t stream);
+hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t stream);
+size_t probe_sink_floats();
+
+}  // namespace rfi

@@ -1,0 +1,288 @@
+"""Thin ctypes binding of librfi (include/rfi.h), with the same names as the C ABI.
+
+Argument marshalling only: every step of the screen runs in the HIP kernels of
+librfi.so.  PyTorch supplies device memory and streams.  Because the C ABI sees
+raw pointers, this layer checks each tensor's device, dtype, contiguity and
+size against the plan before passing its pointer on, so that no kernel is ever
+given a buffer shorter than the plan implies.
+
+The binding fails loudly (RfiError) when librfi.so is missing: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librfi.so")
+
+RFI_OK = 0
+RFI_ERR_INVALID_ARGUMENT = -1
+RFI_ERR_OUT_OF_MEMORY = -2
+RFI_ERR_DEVICE = -3
+RFI_ERR_UNSUPPORTED = -4
+
+RFI_VIS_CF32 = 0
+RFI_VIS_CF16 = 1
+
+RFI_OPT_NO_SK = 1
+RFI_OPT_NO_DS = 2
+RFI_OPT_ADAPTIVE = 4
+
+RFI_FLAG_SK_LOW = 1
+RFI_FLAG_SK_HIGH = 2
+RFI_FLAG_DS_RE = 4
+RFI_FLAG_DS_IM = 8
+
+STATE_RECORD_BYTES = 32
+
+# Every symbol include/rfi.h declares (checked by the CPU test suite).
+EXPORTS = (
+    "rfi_params_default", "rfi_plan_create", "rfi_screen", "rfi_destroy", "rfi_last_error",
+    "rfi_plan_footprint", "rfi_state_bytes", "rfi_state_get", "rfi_state_set",
+    "rfi_state_reset", "rfi_probe_sink_floats", "rfi_probe_read", "rfi_probe_copy",
+)
+
+
+class RfiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"librfi error {code}: {msg}")
+        self.code = code
+
+
+class rfi_params(ctypes.Structure):
+    _fields_ = [
+        ("n_stations", ctypes.c_int32),
+        ("n_baselines", ctypes.c_int32),
+        ("n_channels", ctypes.c_int32),
+        ("n_samples", ctypes.c_int32),
+        ("block_m", ctypes.c_int32),
+        ("vis_format", ctypes.c_int32),
+        ("sk_d", ctypes.c_float),
+        ("sk_low", ctypes.c_float),
+        ("sk_high", ctypes.c_float),
+        ("ds_gamma", ctypes.c_float),
+        ("eps", ctypes.c_float),
+        ("options", ctypes.c_uint32),
+        ("kappa_sk", ctypes.c_float),
+        ("kappa_ds", ctypes.c_float),
+        ("n_warm", ctypes.c_int32),
+        ("block_f", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librfi.so (built by ``__graft_entry__.build()``); raise if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RfiError(RFI_ERR_UNSUPPORTED,
+                       f"{path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    sig = {
+        "rfi_params_default": (None, [P(rfi_params)]),
+        "rfi_plan_create": (ctypes.c_int, [P(rfi_params), ctypes.c_int, P(vp)]),
+        "rfi_screen": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "rfi_destroy": (ctypes.c_int, [vp]),
+        "rfi_last_error": (ctypes.c_char_p, []),
+        "rfi_plan_footprint": (ctypes.c_int, [vp, P(ctypes.c_size_t)]),
+        "rfi_state_bytes": (ctypes.c_size_t, [vp]),
+        "rfi_state_get": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
+        "rfi_state_set": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
+        "rfi_state_reset": (ctypes.c_int, [vp, vp]),
+        "rfi_probe_sink_floats": (ctypes.c_size_t, [ctypes.c_size_t]),
+        "rfi_probe_read": (ctypes.c_int, [vp, ctypes.c_size_t, vp, vp]),
+        "rfi_probe_copy": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != RFI_OK:
+        raise RfiError(rc, rfi_last_error())
+
+
+def rfi_last_error() -> str:
+    return load_library().rfi_last_error().decode()
+
+
+def rfi_params_default(**overrides) -> rfi_params:
+    p = rfi_params()
+    load_library().rfi_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def rfi_plan_create(params: rfi_params, device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(load_library().rfi_plan_create(ctypes.byref(params), device, ctypes.byref(h)))
+    return h.value
+
+
+def rfi_destroy(plan: Optional[int]) -> None:
+    _check(load_library().rfi_destroy(plan))
+
+
+def rfi_plan_footprint(plan: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().rfi_plan_footprint(plan, ctypes.byref(n)))
+    return n.value
+
+
+def rfi_state_bytes(plan: int) -> int:
+    return load_library().rfi_state_bytes(plan)
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def rfi_screen(plan: int, vis, avg, weight, flags=None, stats=None, stream=None) -> None:
+    """Raw entry point: pointers (ints) or tensors, no size checks.  Prefer ``Plan.screen``."""
+    _check(load_library().rfi_screen(plan, _ptr(vis), _ptr(avg), _ptr(weight), _ptr(flags),
+                                     _ptr(stats), _stream_handle(stream)))
+
+
+def rfi_state_get(plan: int, host_buffer) -> None:
+    """Copy the adaptive state into a writable host buffer (numpy array or bytearray)."""
+    import numpy as np
+    a = np.asarray(host_buffer)
+    _check(load_library().rfi_state_get(plan, a.ctypes.data, a.nbytes))
+
+
+def rfi_state_set(plan: int, host_buffer) -> None:
+    import numpy as np
+    a = np.ascontiguousarray(host_buffer)
+    _check(load_library().rfi_state_set(plan, a.ctypes.data, a.nbytes))
+
+
+def rfi_state_reset(plan: int, stream=None) -> None:
+    _check(load_library().rfi_state_reset(plan, _stream_handle(stream)))
+
+
+def rfi_probe_sink_floats(nbytes: int) -> int:
+    return load_library().rfi_probe_sink_floats(nbytes)
+
+
+def rfi_probe_read(src, nbytes: int, sink, stream=None) -> None:
+    _check(load_library().rfi_probe_read(_ptr(src), nbytes, _ptr(sink), _stream_handle(stream)))
+
+
+def rfi_probe_copy(dst, src, nbytes: int, stream=None) -> None:
+    _check(load_library().rfi_probe_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)))
+
+
+# --------------------------------------------------------------------------- checked plan wrapper
+
+class Plan:
+    """A plan with tensor-level checks; outputs allocated with torch on the plan's device."""
+
+    def __init__(self, params: rfi_params, device: int = 0):
+        import torch
+        self.params = params
+        self.device = torch.device("cuda", device)
+        self.handle = rfi_plan_create(params, device)
+        p = params
+        self.B, self.C, self.T, self.M = p.n_baselines, p.n_channels, p.n_samples, p.block_m
+        self.nW = self.T // self.M
+        self.cf16 = p.vis_format == RFI_VIS_CF16
+
+    def close(self):
+        if self.handle is not None:
+            rfi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def vis_shape(self):
+        return (self.B, self.C, self.T, 4, 2)
+
+    def vis_dtype(self):
+        import torch
+        return torch.float16 if self.cf16 else torch.float32
+
+    def footprint(self) -> int:
+        return rfi_plan_footprint(self.handle)
+
+    def alloc_outputs(self, flags: bool = True, stats: bool = False):
+        import torch
+        d = self.device
+        out = dict(avg=torch.empty((self.B, self.C, 4, 2), dtype=torch.float32, device=d),
+                   weight=torch.empty((self.B, self.C), dtype=torch.float32, device=d),
+                   flags=torch.empty((self.B, self.C, self.nW), dtype=torch.uint8, device=d) if flags else None,
+                   stats=torch.empty((self.B, self.C, self.nW, 3), dtype=torch.float32, device=d) if stats else None)
+        return out
+
+    def _check_tensor(self, name, t, shape, dtype):
+        if t is None:
+            return
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} is on {t.device}, plan is on {self.device}")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() != _numel(shape):
+            raise ValueError(f"{name} must have {_numel(shape)} elements {shape}, got {tuple(t.shape)}")
+
+    def screen(self, vis, avg, weight, flags=None, stats=None, stream=None) -> None:
+        import torch
+        self._check_tensor("vis", vis, self.vis_shape, self.vis_dtype())
+        self._check_tensor("avg", avg, (self.B, self.C, 4, 2), torch.float32)
+        self._check_tensor("weight", weight, (self.B, self.C), torch.float32)
+        self._check_tensor("flags", flags, (self.B, self.C, self.nW), torch.uint8)
+        self._check_tensor("stats", stats, (self.B, self.C, self.nW, 3), torch.float32)
+        rfi_screen(self.handle, vis, avg, weight, flags, stats, stream)
+
+    def state(self):
+        """Adaptive state as a numpy structured array [B][C] (n, mean[3], m2[3])."""
+        import numpy as np
+        dt = np.dtype([("n", np.uint32), ("mean", np.float32, 3), ("m2", np.float32, 3), ("reserved", np.uint32)])
+        a = np.zeros((self.B, self.C), dt)
+        rfi_state_get(self.handle, a.view(np.uint8))
+        return a
+
+
+def _numel(shape):
+    n = 1
+    for s in shape:
+        n *= s
+    return n

@@ -1,0 +1,202 @@
+"""GPU parity of librfi's screen against the FP64 oracle (needs an MI355X)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import (TOL_F16_TOTAL, TOL_F32, compare, make_params, run_gpu,
+                               to_device)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_2412_14775_amd import rfi
+    rfi.load_library()
+    yield
+
+
+def thresholds_for(M, d=2.1):
+    """Plan thresholds near the 2.5 / 97.5 % null quantiles (SK) and the 95 % DS quantile."""
+    sd = 1.7 / math.sqrt(M)
+    return dict(d=d, s_low=max(0.05, 1.0 - 2.0 * sd), s_high=1.0 + 2.3 * sd,
+                gamma=min(0.95, math.sqrt(7.815 / (3 * M))))
+
+
+def scene_vis(N, C, T, seed, rfi_channels=(1,), inr=8.0, duty=(40, 7)):
+    env = synth.pulse_train(T, duty[0], duty[1], 3)
+    sc = synth.Scene(N, C, T, seed, rho=0.1,
+                     rfi=[synth.Rfi(list(rfi_channels), inr, 0.7, 0.2, env, f0=0.11)])
+    return synth.correlate(synth.make_voltages(sc))
+
+
+def screen_both(vis, M, fmt="cf32", stats=True, **kw):
+    from paper_2412_14775_amd import rfi
+    B, C, T, _ = vis.shape
+    op, rp = make_params(B, C, T, M, fmt, **kw)
+    plan = rfi.Plan(rp)
+    try:
+        dev = to_device(vis if fmt == "cf32" else synth.to_cf16(vis), fmt)
+        gpu = run_gpu(plan, dev, stats=stats)
+    finally:
+        plan.close()
+    return op, gpu
+
+
+def check_cf16(vis, M, label, **kw):
+    """Complex-half storage: arithmetic error against the oracle on the same FP16 bytes
+    (1e-5, every M) and total error against the oracle on the original complex64 input
+    (3e-3).  The total bound is asserted for M >= 16: for M < 16 the storage rounding
+    alone, amplified by (Md+1)/(M-1), can exceed it whatever the kernel does."""
+    op, gpu = screen_both(vis, M, "cf16", **kw)
+    rep_a = compare(gpu, synth.to_cf16(vis), op, TOL_F32, label=label + " (fp16 input)")
+    rep_t = compare(gpu, vis, op, TOL_F16_TOTAL, label=label + " (original input)") if M >= 16 else None
+    return rep_a, rep_t
+
+
+# ----------------------------------------------------------------------------- the plain case
+
+def test_plain_case_cf32():
+    vis = synth.correlate(synth.make_voltages(synth.scene_plain(0)))
+    op, gpu = screen_both(vis, 16, **thresholds_for(16))
+    rep = compare(gpu, vis, op, TOL_F32, label="plain cf32")
+    print("plain cf32", rep)
+    assert 0.05 < rep["flagged_frac"] < 0.6
+
+
+def test_plain_case_cf16():
+    vis = synth.correlate(synth.make_voltages(synth.scene_plain(0)))
+    rep_a, rep_t = check_cf16(vis, 16, "plain cf16", **thresholds_for(16))
+    print("plain cf16", rep_a, rep_t)
+
+
+# ----------------------------------------------------------------------------- window lengths
+
+@pytest.mark.parametrize("fmt", ["cf32", "cf16"])
+@pytest.mark.parametrize("M", [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048])
+def test_power_of_two_windows(fmt, M):
+    T = M * max(3, 1600 // M)         # several steps per stream and a ragged last step
+    vis = scene_vis(2, 5, T, seed=M)
+    if fmt == "cf32":
+        op, gpu = screen_both(vis, M, **thresholds_for(M))
+        compare(gpu, vis, op, TOL_F32, label=f"cf32 M={M}")
+    else:
+        check_cf16(vis, M, f"cf16 M={M}", **thresholds_for(M))
+
+
+@pytest.mark.parametrize("fmt", ["cf32", "cf16"])
+@pytest.mark.parametrize("M,T", [(3, 300), (10, 400), (20, 3060), (48, 960), (100, 500)])
+def test_other_window_lengths(fmt, M, T):
+    vis = scene_vis(2, 3, T, seed=M + 7, duty=(60, 20))
+    if fmt == "cf32":
+        op, gpu = screen_both(vis, M, **thresholds_for(M))
+        compare(gpu, vis, op, TOL_F32, label=f"cf32 M={M}")
+    else:
+        check_cf16(vis, M, f"cf16 M={M}", **thresholds_for(M))
+
+
+@pytest.mark.parametrize("fmt", ["cf32", "cf16"])
+@pytest.mark.parametrize("M,T", [(16, 4096), (64, 1088), (64, 3072), (256, 3072)])
+def test_few_long_streams_split_over_waves(fmt, M, T):
+    """A handful of streams: each is split over several waves whose partial sums are combined."""
+    vis = scene_vis(1, 3, T, seed=T + M)
+    if fmt == "cf32":
+        op, gpu = screen_both(vis, M, **thresholds_for(M))
+        compare(gpu, vis, op, TOL_F32, label=f"segmented cf32 M={M} T={T}")
+    else:
+        check_cf16(vis, M, f"segmented cf16 M={M} T={T}", **thresholds_for(M))
+
+
+# ----------------------------------------------------------------------------- edge cases
+
+@pytest.mark.parametrize("fmt", ["cf32", "cf16"])
+def test_degenerate_inputs(fmt):
+    M, T = 16, 256
+    vis = scene_vis(2, 4, T, seed=3).astype(np.complex64)
+    vis[0, 0] = 0                                  # all-zero stream: every window SK_LOW
+    vis[1, 1, 20, 2] = np.nan                      # NaN sample: its window flagged
+    vis[2, 2, 100, 0] = np.inf                     # Inf sample
+    vis[2, 3, 33:48] = 0                           # a partly zero window
+    op, gpu = screen_both(vis, M, fmt, **thresholds_for(M))
+    ref_vis = vis if fmt == "cf32" else synth.to_cf16(vis)
+    compare(gpu, ref_vis, op, TOL_F32, label=f"degenerate {fmt}")
+    assert np.all(gpu["flags"][0, 0] == oracle.SK_LOW)
+    assert gpu["weight"][0, 0] == 0.0 and np.all(gpu["avg"][0, 0] == 0)
+    assert gpu["flags"][1, 1, 1] != 0 and np.isfinite(gpu["avg"]).all()
+
+
+def test_single_window_and_single_station():
+    vis = scene_vis(1, 2, 64, seed=9)              # N = 1: one autocorrelation stream per channel
+    op, gpu = screen_both(vis, 64, **thresholds_for(64))
+    compare(gpu, vis, op, TOL_F32, label="T = M")
+    assert np.all(gpu["r_im"] == 0.0)              # autos are Hermitian
+
+
+@pytest.mark.parametrize("options", [oracle.OPT_NO_SK, oracle.OPT_NO_DS, oracle.OPT_NO_SK | oracle.OPT_NO_DS])
+def test_options_disable_tests(options):
+    vis = scene_vis(2, 4, 512, seed=4, inr=15.0)
+    op, gpu = screen_both(vis, 16, options=options, **thresholds_for(16))
+    compare(gpu, vis, op, TOL_F32, label=f"options {options}")
+    if options & oracle.OPT_NO_SK:
+        assert not np.any(gpu["flags"] & 3)
+    if options & oracle.OPT_NO_DS:
+        assert not np.any(gpu["flags"] & 12)
+
+
+@pytest.mark.parametrize("fmt", ["cf32", "cf16"])
+def test_dynamic_range_fuzz(fmt):
+    """Circular-Gaussian correlations scaled by 10^U(-2, 3) per window, with random
+    rank-one RFI blocks mixed by a random 2x2 complex matrix (the precision-search
+    data distribution of Section 4.1)."""
+    rng = np.random.default_rng(77)
+    B, C, T, M = 6, 4, 640, 16
+    z = (rng.standard_normal((B, C, T, 4)) + 1j * rng.standard_normal((B, C, T, 4))) / math.sqrt(2)
+    scale = 10.0 ** rng.uniform(-2, 3, (B, C, T // M, 1, 1))
+    vis = (z.reshape(B, C, T // M, M, 4) * scale)
+    hit = rng.random((B, C, T // M)) < 0.4
+    J = (rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))) / math.sqrt(2)
+    rfi_block = (J @ J.conj().T).reshape(4) * (10.0 ** rng.uniform(-2, 3, (B, C, T // M, 1, 1)))
+    vis = vis + hit[..., None, None] * rfi_block
+    vis = vis.reshape(B, C, T, 4).astype(np.complex64)
+    op, gpu = screen_both(vis, M, fmt, **thresholds_for(M))
+    compare(gpu, vis if fmt == "cf32" else synth.to_cf16(vis), op, TOL_F32, label=f"fuzz {fmt}")
+
+
+def test_repeatable_bitwise():
+    from paper_2412_14775_amd import rfi
+    vis = scene_vis(3, 8, 1024, seed=5)
+    B, C, T, _ = vis.shape
+    op, rp = make_params(B, C, T, 64, **thresholds_for(64))
+    plan = rfi.Plan(rp)
+    dev = to_device(vis, "cf32")
+    a = run_gpu(plan, dev)
+    b = run_gpu(plan, dev)
+    plan.close()
+    for k in ("avg", "weight", "flags", "stats32"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_outputs_optional():
+    vis = scene_vis(2, 3, 256, seed=6)
+    op, gpu = screen_both(vis, 16, stats=False, **thresholds_for(16))
+    compare(gpu, vis, op, TOL_F32, label="no stats")
+
+
+def test_size_checks_in_binding():
+    import torch
+    from paper_2412_14775_amd import rfi
+    op, rp = make_params(3, 2, 64, 16)
+    plan = rfi.Plan(rp)
+    out = plan.alloc_outputs()
+    short = torch.zeros((3, 2, 63, 4, 2), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(ValueError):
+        plan.screen(short, out["avg"], out["weight"], out["flags"])
+    wrong = torch.zeros((3, 2, 64, 4, 2), dtype=torch.float16, device="cuda:0")
+    with pytest.raises(ValueError):
+        plan.screen(wrong, out["avg"], out["weight"], out["flags"])
+    plan.close()
