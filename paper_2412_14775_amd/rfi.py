@@ -87,7 +87,15 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RfiError(RFI_ERR_UNSUPPORTED,
                        f"{path} is missing: build it with __graft_entry__.build()")
+    # PyTorch ships its own HIP runtime (soname libamdhip64.so.7).  Loading torch
+    # first makes librfi's dependency on that soname bind to the same runtime, so
+    # device pointers and stream handles from torch are valid inside librfi.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
+    runtimes = hip_runtimes_loaded()
+    if len(runtimes) > 1:
+        raise RfiError(RFI_ERR_DEVICE, "two HIP runtimes are loaded in this process "
+                       f"({', '.join(sorted(runtimes))}); import torch before loading librfi")
     P = ctypes.POINTER
     vp = ctypes.c_void_p
     sig = {
@@ -111,6 +119,19 @@ def load_library(path: str = LIB_PATH):
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def hip_runtimes_loaded():
+    """Distinct libamdhip64 files mapped into this process."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        pass
+    return paths
 
 
 def _check(rc: int):

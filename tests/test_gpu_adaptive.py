@@ -1,0 +1,71 @@
+"""Per-stream adaptive thresholds (RFI_OPT_ADAPTIVE) against the oracle's running state."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import TOL_F32, compare, make_params, run_gpu, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _integration(i, N=2, C=8, T=1024):
+    env = synth.pulse_train(T, 200, 30, 17 * i)
+    sc = synth.Scene(N, C, T, seed=100 + i, rho=0.1,
+                     rfi=[synth.Rfi([2 % C, 5 % C], 6.0 + i, 0.3 * i, 0.1, env, f0=0.07)])
+    return synth.correlate(synth.make_voltages(sc))
+
+
+@pytest.mark.parametrize("fmt,M", [("cf32", 16), ("cf16", 64), ("cf32", 20)])
+def test_adaptive_thresholds_follow_oracle_state(fmt, M):
+    from paper_2412_14775_amd import rfi
+    B, C, T = 3, 8, 1280 if M == 20 else 1024
+    kw = dict(d=2.1, s_low=0.2, s_high=2.6, gamma=0.5, kappa_sk=3.0, kappa_ds=3.0,
+              n_warm=80, options=oracle.OPT_ADAPTIVE)
+    op, rp = make_params(B, C, T, M, fmt, **kw)
+    plan = rfi.Plan(rp)
+    state = oracle.AdaptiveState((B, C))
+    warm_seen = False
+    for i in range(6):
+        vis = _integration(i, T=T)
+        ref_in = vis if fmt == "cf32" else synth.to_cf16(vis)
+        gpu = run_gpu(plan, to_device(ref_in, fmt))
+        th = state.thresholds(op)
+        warm_seen |= bool(np.any(state.n >= 80))
+        th_b = {k: np.asarray(v)[..., None] for k, v in th.items()}
+        ref = oracle.screen(ref_in, op, th_b)
+        compare(gpu, ref_in, op, TOL_F32, thresholds=th, ref=ref, label=f"adaptive {fmt} M={M} it={i}")
+        # conditional parity of the state: the oracle merges the windows the GPU kept
+        st = np.stack([ref["tau"], ref["r_re"], ref["r_im"]], -1)
+        state.update(st, gpu["flags"] == 0)
+        g = plan.state()
+        assert np.array_equal(g["n"], state.n), f"it={i}: window counts differ"
+        np.testing.assert_allclose(g["mean"], state.mean, rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(g["m2"], state.m2, rtol=1e-4, atol=1e-6)
+    assert warm_seen
+    plan.close()
+
+
+def test_state_checkpoint_roundtrip_and_reset():
+    from paper_2412_14775_amd import rfi
+    import torch
+    B, C, T, M = 3, 4, 512, 16
+    op, rp = make_params(B, C, T, M, options=oracle.OPT_ADAPTIVE, n_warm=2, kappa_sk=1.0, kappa_ds=1.0)
+    plan = rfi.Plan(rp)
+    st = plan.state()
+    assert st.nbytes == rfi.rfi_state_bytes(plan.handle) == B * C * 32
+    assert np.all(st["n"] == 0)
+    # a resumed state with tight thresholds around tau = 1, r = 0: almost everything flagged
+    st["n"] = 1000
+    st["mean"] = (1.0, 0.0, 0.0)
+    st["m2"] = (1e-6 * 999, 1e-8 * 999, 1e-8 * 999)
+    rfi.rfi_state_set(plan.handle, st.view(np.uint8))
+    back = plan.state()
+    assert np.array_equal(back.view(np.uint8), st.view(np.uint8))
+    vis = _integration(0, C=C, T=T)
+    gpu = run_gpu(plan, to_device(vis, "cf32"))
+    assert (gpu["flags"] != 0).mean() > 0.9
+    rfi.rfi_state_reset(plan.handle)
+    torch.cuda.synchronize()
+    assert np.all(plan.state()["n"] == 0)
+    plan.close()

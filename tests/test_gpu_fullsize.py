@@ -1,0 +1,121 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+
+The GPU screens the whole array; the FP64 oracle recomputes a seeded sample of
+streams (all autocorrelations, every RFI channel of a set of cross baselines,
+and random streams), from the exact bytes copied back from the device.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import TOL_F16_TOTAL, TOL_F32, compare
+
+pytestmark = pytest.mark.gpu
+
+PLAN64 = dict(d=2.2, s_low=0.656, s_high=1.487, gamma=0.202)
+
+
+def _device_array(scene, fmt):
+    import torch
+    e = torch.from_numpy(synth.make_voltages(scene)).cuda()
+    B, C, T = scene.n_baselines, scene.n_channels, scene.n_samples
+    vis = torch.empty((B, C, T, 4, 2), dtype=torch.float16 if fmt == "cf16" else torch.float32, device="cuda:0")
+    synth.correlate_torch(e, vis, fmt)
+    del e
+    return vis
+
+
+def _screen(vis, scene, M, fmt, **thr):
+    import torch
+    from paper_2412_14775_amd import rfi
+    params = rfi.rfi_params_default(
+        n_stations=scene.n_stations, n_baselines=scene.n_baselines, n_channels=scene.n_channels,
+        n_samples=scene.n_samples, block_m=M,
+        vis_format=rfi.RFI_VIS_CF16 if fmt == "cf16" else rfi.RFI_VIS_CF32,
+        sk_d=thr["d"], sk_low=thr["s_low"], sk_high=thr["s_high"], ds_gamma=thr["gamma"])
+    plan = rfi.Plan(params)
+    out = plan.alloc_outputs(flags=True, stats=True)
+    plan.screen(vis, out["avg"], out["weight"], out["flags"], out["stats"])
+    torch.cuda.synchronize()
+    plan.close()
+    return out
+
+
+def _sample_streams(scene, rng, n_random):
+    B, C = scene.n_baselines, scene.n_channels
+    p, q = synth.baseline_pairs(scene.n_stations)
+    autos = np.where(p == q)[0]
+    rfi_ch = sorted({c for s in scene.rfi for c in s.channels if len(s.channels) < C})
+    picks = [(b, c) for b in autos[:: max(1, len(autos) // 8)] for c in range(0, C, max(1, C // 8))]
+    crosses = rng.choice(np.where(p != q)[0], 8, replace=False)
+    picks += [(b, c) for b in crosses for c in rfi_ch]
+    picks += list(zip(rng.integers(0, B, n_random), rng.integers(0, C, n_random)))
+    return np.array(sorted(set((int(b), int(c)) for b, c in picks)))
+
+
+def _gather(out, vis, idx):
+    import torch
+    b = torch.as_tensor(idx[:, 0], device="cuda:0")
+    c = torch.as_tensor(idx[:, 1], device="cuda:0")
+    v = vis[b, c].cpu().numpy()                                   # [S, T, 4, 2]
+    g = {}
+    avg = out["avg"][b, c].cpu().numpy()
+    g["avg"] = (avg[..., 0].astype(np.float64) + 1j * avg[..., 1])[:, None]
+    g["weight"] = out["weight"][b, c].cpu().numpy()[:, None]
+    g["flags"] = out["flags"][b, c].cpu().numpy()[:, None]
+    st = out["stats"][b, c].cpu().numpy()[:, None]
+    g["stats32"] = st
+    g["tau"], g["r_re"], g["r_im"] = (st[..., k].astype(np.float64) for k in range(3))
+    return v[:, None], g                                          # vis [S, 1, T, 4, 2]
+
+
+def test_fp32_baseline_and_fp16_form_full_size():
+    """48 stations, 64 channels, 3072 samples, M = 64: complex64 and complex-half storage."""
+    import torch
+    scene = synth.scene_fp32_baseline(1)
+    vis32 = _device_array(scene, "cf32")
+    out32 = _screen(vis32, scene, 64, "cf32", **PLAN64)
+    rng = np.random.default_rng(0)
+    idx = _sample_streams(scene, rng, 256)
+    op = oracle.Params(M=64, **PLAN64)
+    v32, g32 = _gather(out32, vis32, idx)
+    rep32 = compare(g32, v32, op, TOL_F32, label="fp32 baseline")
+    print("fp32 baseline sampled", len(idx), "streams", rep32)
+
+    vis16 = vis32.to(torch.float16)
+    out16 = _screen(vis16, scene, 64, "cf16", **PLAN64)
+    v16, g16 = _gather(out16, vis16, idx)
+    rep_a = compare(g16, v16, op, TOL_F32, label="fp16 form vs oracle on fp16 bytes")
+    rep_t = compare(g16, v32, op, TOL_F16_TOTAL, label="fp16 form vs oracle on complex64 bytes")
+    disagree = (out16["flags"] != out32["flags"]).float().mean().item()
+    print("fp16 form", rep_a, rep_t, "flag disagreement vs complex64 run", disagree)
+    assert disagree < 0.01          # the paper reports < 1 % between 32-bit and mixed precision
+
+
+@pytest.fixture(scope="module")
+def mixed_case():
+    import torch
+    scene = synth.scene_mixed(3)
+    vis16 = _device_array(scene, "cf16")
+    yield scene, vis16
+    del vis16
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("M", [16, 64, 256])
+def test_mixed_rfi_large_case_fp16(mixed_case, M):
+    """64 stations (2080 baselines), 256 channels, 3072 samples, complex half, 26.2 GB:
+    CW, radar pulse trains, broadband bursts, 20 %-polarised sky.  The oracle covers
+    a seeded sample of at least 1 % of the streams."""
+    scene, vis16 = mixed_case
+    sd = 1.7 / np.sqrt(M)
+    thr = dict(d=2.2, s_low=1 - 2 * sd, s_high=1 + 2.3 * sd, gamma=float(np.sqrt(7.815 / (3 * M))))
+    out = _screen(vis16, scene, M, "cf16", **thr)
+    rng = np.random.default_rng(M)
+    n_streams = scene.n_baselines * scene.n_channels
+    idx = _sample_streams(scene, rng, n_streams // 100)
+    assert len(idx) >= n_streams // 100
+    v, g = _gather(out, vis16, idx)
+    rep = compare(g, v, oracle.Params(M=M, **thr), TOL_F32, label=f"mixed case M={M}")
+    print(f"mixed case M={M}", len(idx), "streams", rep)
