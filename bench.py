@@ -140,6 +140,22 @@ def probe_bandwidth(vis_bytes_tensor, nbytes, stream, reps=10):
     return nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
 
 
+COPY_CALIBRATION_BYTES = 1 << 30
+
+
+def copy_calibration(buf, stream, reps=3):
+    """A plain copy of exactly 1 GiB (read 1 GiB, write 1 GiB): the known-traffic kernel
+    against which the hardware byte counters of a profiling run are scaled."""
+    import torch
+    from paper_2412_14775_amd import rfi
+    n = COPY_CALIBRATION_BYTES
+    flat = buf.view(torch.uint8).view(-1)
+    assert flat.numel() >= 2 * n
+    for _ in range(reps):
+        rfi.rfi_probe_copy(flat[n:2 * n], flat[:n], n, stream)
+    torch.cuda.synchronize()
+
+
 def stored_traffic(digest: str, per_launch_alg: float):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
     this exact kernel source; None otherwise."""
@@ -210,6 +226,7 @@ def main(argv=None):
             "host_wall_s": wall,
         }
     probe = probe_bandwidth(vis32, vis32.numel() * 4, stream)
+    copy_calibration(vis32, stream)
 
     f32 = forms["cf32"]
     digest = kernel_source_digest()

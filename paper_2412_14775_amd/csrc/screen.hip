@@ -37,6 +37,9 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 constexpr int kPieces = 8;                    // 16-byte pieces per lane per step
 constexpr int kTilePieces = kWave * kPieces;  // 8 KiB per wave per step
 constexpr int kRsrcWord3 = 0x00020000;        // raw buffer, 32-bit data format
+// Cache policy of the visibility loads: non-temporal (every byte is read exactly
+// once, so it should not displace anything in L2 / the infinity cache).
+constexpr int kLoadStreaming = 2;
 
 __device__ __forceinline__ int lds_slot(int p) { return p ^ (((p >> 3) ^ (p >> 6)) & 7); }
 
@@ -310,7 +313,7 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
       for (int i = 0; i < kPieces; ++i)
         buf[i] = __builtin_bit_cast(
             u32x4, __builtin_amdgcn_raw_buffer_load_b128(
-                       rsrc, (unsigned)(step * SPI * SB + (i * kWave + lane) * 16), 0, 0));
+                       rsrc, (unsigned)(step * SPI * SB + (i * kWave + lane) * 16), 0, kLoadStreaming));
     };
 
     float ws[8] = {}, wr[8] = {};
@@ -384,12 +387,12 @@ __global__ void __launch_bounds__(kBlock) screen_generic(const ScreenArgs a) {
         const unsigned off = (unsigned)((w * a.M + t) * SB);
         float x[8];
         if constexpr (FMT == FMT_CF32) {
-          const f32x4 lo = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0));
-          const f32x4 hi = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + 16, 0, 0));
+          const f32x4 lo = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
+          const f32x4 hi = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + 16, 0, kLoadStreaming));
           x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
           x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
         } else {
-          const f16x8 h = __builtin_bit_cast(f16x8, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0));
+          const f16x8 h = __builtin_bit_cast(f16x8, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
 #pragma unroll
           for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
         }
