@@ -170,12 +170,89 @@ def stored_traffic(digest: str, per_launch_alg: float):
     return t.get("cf32_bytes_per_launch")
 
 
+def serving(seconds: float, rate: float):
+    """Serving form: 16 arrays (12-64 stations, 16-256 channels, M = 64, complex half,
+    adaptive thresholds), inputs pre-staged in HBM; Poisson arrivals at `rate` per second in
+    total for `seconds`, then the same requests all at once (saturated)."""
+    import torch
+    from paper_2412_14775_amd import rfi
+    scenes = synth.serving_mix()
+    dev = torch.device("cuda:0")
+    arrays = []
+    for sc in scenes:
+        e = synth.device_voltages(sc, dev)
+        vis = torch.empty((sc.n_baselines, sc.n_channels, sc.n_samples, 4, 2), dtype=torch.float16, device=dev)
+        synth.correlate_torch(e, vis, "cf16")
+        del e
+        params = rfi.rfi_params_default(n_stations=sc.n_stations, n_baselines=sc.n_baselines,
+                                        n_channels=sc.n_channels, n_samples=sc.n_samples, block_m=64,
+                                        vis_format=rfi.RFI_VIS_CF16, options=rfi.RFI_OPT_ADAPTIVE,
+                                        n_warm=64, **PLAN)
+        plan = rfi.Plan(params)
+        arrays.append((sc, plan, vis, plan.alloc_outputs(flags=True, stats=False)))
+    torch.cuda.synchronize()
+    samples = [sc.n_baselines * sc.n_channels * sc.n_samples for sc, *_ in arrays]
+    nbytes = [s * 16 for s in samples]
+    srv = rfi.Server(n_slots=16, hbm_budget=200 << 30)
+    tag = 0
+    for i, (sc, plan, vis, out) in enumerate(arrays):                 # capture every graph once
+        srv.submit(plan, vis, out, tag=tag)
+        tag += 1
+    srv.drain(120)
+    srv.poll(10000)
+
+    def run(arrivals):
+        nonlocal tag
+        first = tag
+        for t, i in arrivals:
+            sc, plan, vis, out = arrays[i]
+            srv.submit(plan, vis, out, arrival=t, tag=tag)
+            tag += 1
+        srv.drain(600)
+        done = [c for c in srv.poll(100000) if c["tag"] >= first]
+        assert len(done) == len(arrivals) and all(c["status"] == 0 for c in done)
+        lat = np.array([c["done"] - c["arrival"] for c in done])
+        span = max(c["done"] for c in done) - min(c["arrival"] for c in done)
+        idx = [arrivals[c["tag"] - first][1] for c in done]
+        return lat, span, sum(samples[i] for i in idx), sum(nbytes[i] for i in idx)
+
+    rng = np.random.default_rng(11)
+    t, arr = srv.now() + 0.05, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > srv.now() + 0.05 + seconds:
+            break
+        arr.append((t, int(rng.integers(0, len(arrays)))))
+    lat, span, n_s, n_b = run(arr)
+    t0 = srv.now()
+    sat = [(t0, i) for i in range(len(arrays)) for _ in range(4)]
+    lat_s, span_s, n_s2, n_b2 = run(sat)
+    st = srv.stats()
+    srv.close()
+    for _, plan, *_ in arrays:
+        plan.close()
+    return {
+        "arrays": [[sc.n_stations, sc.n_channels] for sc, *_ in arrays],
+        "pool_GB": sum(nbytes) / 1e9,
+        "requests": len(arr), "rate_per_s": rate, "deadline_ms": 1000.0,
+        "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "max_ms": float(lat.max() * 1e3), "deadline_misses": int((lat > 1.0).sum()),
+        "offered_samples_per_s": n_s / span,
+        "saturated": {"requests": len(sat), "makespan_ms": span_s * 1e3,
+                      "samples_per_s": n_s2 / span_s, "GBs": n_b2 / span_s / 1e9,
+                      "p99_ms": float(np.percentile(lat_s, 99) * 1e3)},
+        "peak_inflight": st["peak_inflight"], "graphs": st["graphs"],
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=6.0,
+                    help="length of the real-time serving run (0 skips the serving form)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: only --gpus 1 is supported (got {args.gpus}); the screen shards by "
@@ -227,6 +304,9 @@ def main(argv=None):
         }
     probe = probe_bandwidth(vis32, vis32.numel() * 4, stream)
     copy_calibration(vis32, stream)
+    del vis32, vis16
+    torch.cuda.empty_cache()
+    serve = serving(args.serving_seconds, 16.0) if args.serving_seconds > 0 else None
 
     f32 = forms["cf32"]
     digest = kernel_source_digest()
@@ -258,6 +338,7 @@ def main(argv=None):
                                                "achieved_GBs", "hbm_frac")},
         "cf16_over_cf32": forms["cf16"]["samples_per_s"] / f32["samples_per_s"],
         "read_probe_GBs": probe,
+        "serving": serve,
         "flagged_frac": f32["flagged_frac"],
         "kernel_source_digest": digest,
     }

@@ -163,6 +163,75 @@ int rfi_probe_read(const void *src, size_t bytes, float *sink, void *hip_stream)
  * calibrate hardware byte counters. */
 int rfi_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Serving: a persistent request loop that screens integrations of many arrays as they
+ * arrive (continuous batching).  Not a paper passage: it serves the online use the paper
+ * targets (Section 1: real time, before averaging, in the correlator).
+ *
+ * A request names a plan (one per array stream; its adaptive state lives on the device)
+ * and that integration's device buffers, plus an arrival time on the server clock.  A
+ * scheduler thread releases requests at their arrival time into a FIFO queue and admits
+ * a request when (a) a slot (one HIP stream each) is free, (b) the footprint of all
+ * admitted requests plus this one's (rfi_plan_footprint) stays within the HBM budget, and
+ * (c) no earlier request of the same plan is still queued or running (per-plan order keeps
+ * the adaptive state update sequence of that array).  A request that cannot be admitted
+ * does not block later requests of other plans.  Each admitted request replays a hipGraph
+ * of its screen step (captured on first use for that plan and buffer set) on its slot's
+ * stream; a host callback timestamps completion.  Requests of different arrays therefore
+ * overlap on the device, and each result is bitwise the same as when run alone.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct rfi_server rfi_server; /* opaque */
+
+typedef struct rfi_server_config {
+  int32_t device;          /* HIP device                                                      */
+  int32_t n_slots;         /* requests on the device at once (HIP streams), 1..64               */
+  uint64_t hbm_budget;     /* bytes: cap on the summed footprint of admitted requests, > 0      */
+  int32_t use_graphs;      /* 1: replay captured hipGraphs; 0: launch rfi_screen directly       */
+} rfi_server_config;
+
+typedef struct rfi_request {
+  rfi_plan *plan;          /* not owned; must outlive the request                               */
+  const void *vis;         /* device buffers as for rfi_screen (flags / stats may be NULL)      */
+  float *avg;
+  float *weight;
+  uint8_t *flags;
+  float *stats;
+  double arrival;          /* server clock, seconds (rfi_server_now); past values = now         */
+  uint64_t tag;            /* caller's identifier, returned in the completion                   */
+} rfi_request;
+
+typedef struct rfi_completion {
+  uint64_t tag;
+  int32_t status;          /* RFI_OK or the error of the launch                                 */
+  int32_t slot;            /* slot (stream) the request ran on                                  */
+  double arrival;          /* server clock, seconds                                             */
+  double admitted;         /* when the scheduler launched it                                    */
+  double done;             /* when the device finished it (host callback)                       */
+} rfi_completion;
+
+typedef struct rfi_server_stats {
+  uint64_t submitted, completed, failed;
+  uint64_t peak_inflight_bytes;  /* largest summed footprint of admitted requests                */
+  int32_t peak_inflight;         /* largest number of requests on the device at once            */
+  int32_t graphs;                /* graphs captured so far                                      */
+} rfi_server_stats;
+
+/* Create the server and start its scheduler thread.  Errors: INVALID_ARGUMENT, DEVICE. */
+int rfi_server_create(const rfi_server_config *cfg, rfi_server **out);
+/* Seconds since the server was created (monotonic clock). */
+double rfi_server_now(const rfi_server *srv);
+/* Queue a request (thread-safe; returns at once).  INVALID_ARGUMENT if a pointer is NULL or
+ * the plan's footprint alone exceeds the budget (the request could never be admitted). */
+int rfi_server_submit(rfi_server *srv, const rfi_request *req);
+/* Move up to `max` completions into `out` (*n_out of them), waiting up to timeout_s seconds
+ * for at least one.  Completions are returned in the order the device finished them. */
+int rfi_server_poll(rfi_server *srv, rfi_completion *out, int32_t max, int32_t *n_out, double timeout_s);
+/* Block until every submitted request has completed (or timeout_s passes: then DEVICE). */
+int rfi_server_drain(rfi_server *srv, double timeout_s);
+int rfi_server_get_stats(const rfi_server *srv, rfi_server_stats *out);
+/* Stop the scheduler after draining, free streams and graphs.  NULL-safe. */
+int rfi_server_destroy(rfi_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,16 @@ int choose_segments(const rfi_params &p, int64_t n_streams) {
 
 }  // namespace
 
+int rfi::set_error(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
 extern "C" {
 
 void rfi_params_default(rfi_params *p) {

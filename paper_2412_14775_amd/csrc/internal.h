@@ -55,6 +55,9 @@ hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream);
 int tiled_samples_per_lane(int fmt);
 bool tiled_supports(int M);
 
+// Records the thread's last error (read back by rfi_last_error) and returns `code`.
+int set_error(int code, const char *fmt, ...);
+
 hipError_t launch_probe_read(const void *src, size_t bytes, float *sink, hipStream_t stream);
 hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t stream);
 size_t probe_sink_floats();

@@ -1,0 +1,333 @@
+// serve.hip -- the persistent request loop of librfi (rfi_server_*, include/rfi.h).
+//
+// One scheduler thread owns the queues.  Requests wait in a time-ordered set
+// until their arrival time, then in a FIFO queue until a slot (a HIP stream)
+// is free and the summed footprint of admitted requests leaves room for them;
+// requests of one plan stay in order.  An admitted request replays a captured
+// hipGraph of its screen step on its slot's stream, followed by a host
+// callback that timestamps completion and frees the slot.  The callback takes
+// the server mutex only briefly and never calls into HIP.
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <new>
+#include <set>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "../../include/rfi.h"
+#include "internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct GraphKey {
+  const void *plan, *vis, *avg, *weight, *flags, *stats;
+  bool operator<(const GraphKey &o) const {
+    return std::tie(plan, vis, avg, weight, flags, stats) < std::tie(o.plan, o.vis, o.avg, o.weight, o.flags, o.stats);
+  }
+};
+
+struct Pending {
+  rfi_request req;
+  uint64_t bytes;
+  uint64_t seq;
+};
+
+struct SlotCtx {
+  rfi_server *srv;
+  int slot;
+};
+
+int set_error(int code, const char *msg) { return rfi::set_error(code, "%s", msg); }
+
+}  // namespace
+
+struct rfi_server {
+  rfi_server_config cfg{};
+  Clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv_sched;
+  std::condition_variable cv_done;
+  std::multimap<double, Pending> future;   // not yet arrived
+  std::deque<Pending> queue;               // arrived, waiting for admission
+  std::vector<hipStream_t> streams;
+  std::vector<bool> slot_busy;
+  std::vector<const rfi_plan *> slot_plan;
+  std::vector<uint64_t> slot_bytes;
+  std::vector<rfi_completion> slot_rec;
+  std::vector<SlotCtx> ctx;
+  std::deque<rfi_completion> done;
+  std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  uint64_t inflight_bytes = 0;
+  int inflight = 0;
+  uint64_t outstanding = 0;
+  uint64_t seq = 0;
+  uint64_t events = 0;  // bumped by every submit and completion: the scheduler re-plans on change
+  rfi_server_stats stats{};
+  std::atomic<int> n_graphs{0};
+  bool stop = false;
+  std::thread thread;
+
+  double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+  void run();
+  int launch(int slot, const rfi_request &r);
+  static void on_done(void *p);
+};
+
+// Host callback after a request's graph: runs on a runtime thread, no HIP calls.
+void rfi_server::on_done(void *p) {
+  SlotCtx *c = static_cast<SlotCtx *>(p);
+  rfi_server *s = c->srv;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    rfi_completion rec = s->slot_rec[c->slot];
+    rec.done = s->now();
+    s->done.push_back(rec);
+    s->slot_busy[c->slot] = false;
+    s->slot_plan[c->slot] = nullptr;
+    s->inflight_bytes -= s->slot_bytes[c->slot];
+    s->inflight -= 1;
+    s->outstanding -= 1;
+    s->stats.completed += 1;
+    s->events += 1;
+  }
+  s->cv_sched.notify_one();
+  s->cv_done.notify_all();
+}
+
+int rfi_server::launch(int slot, const rfi_request &r) {
+  hipStream_t st = streams[slot];
+  if (!cfg.use_graphs) return rfi_screen(r.plan, r.vis, r.avg, r.weight, r.flags, r.stats, st);
+  const GraphKey key{r.plan, r.vis, r.avg, r.weight, r.flags, r.stats};
+  auto it = graphs.find(key);
+  if (it == graphs.end()) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return set_error(RFI_ERR_DEVICE, "hipStreamBeginCapture failed");
+    const int rc = rfi_screen(r.plan, r.vis, r.avg, r.weight, r.flags, r.stats, st);
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc != RFI_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != RFI_OK ? rc : set_error(RFI_ERR_DEVICE, "hipStreamEndCapture failed");
+    }
+    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return set_error(RFI_ERR_DEVICE, "hipGraphInstantiate failed");
+    }
+    it = graphs.emplace(key, std::make_pair(g, ge)).first;
+    n_graphs.fetch_add(1);
+  }
+  if (hipGraphLaunch(it->second.second, st) != hipSuccess) return set_error(RFI_ERR_DEVICE, "hipGraphLaunch failed");
+  return RFI_OK;
+}
+
+void rfi_server::run() {
+  (void)hipSetDevice(cfg.device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    const uint64_t seen = events;
+    const double t = now();
+    while (!future.empty() && future.begin()->first <= t) {
+      queue.push_back(future.begin()->second);
+      future.erase(future.begin());
+    }
+    // admission: FIFO, skipping requests that cannot go yet; a plan stays in order
+    std::set<const rfi_plan *> blocked;
+    for (auto it = queue.begin(); it != queue.end();) {
+      const rfi_plan *plan = it->req.plan;
+      bool plan_busy = blocked.count(plan) > 0;
+      for (int s = 0; s < cfg.n_slots && !plan_busy; ++s) plan_busy = slot_busy[s] && slot_plan[s] == plan;
+      if (plan_busy || inflight_bytes + it->bytes > cfg.hbm_budget) {
+        blocked.insert(plan);
+        ++it;
+        continue;
+      }
+      int slot = -1;
+      for (int s = 0; s < cfg.n_slots; ++s)
+        if (!slot_busy[s]) {
+          slot = s;
+          break;
+        }
+      if (slot < 0) break;
+      const Pending p = *it;
+      it = queue.erase(it);  // only this thread touches `queue`: `it` stays valid across the unlock
+      slot_busy[slot] = true;
+      slot_plan[slot] = plan;
+      slot_bytes[slot] = p.bytes;
+      inflight_bytes += p.bytes;
+      inflight += 1;
+      if (inflight_bytes > stats.peak_inflight_bytes) stats.peak_inflight_bytes = inflight_bytes;
+      if (inflight > stats.peak_inflight) stats.peak_inflight = inflight;
+      rfi_completion &rec = slot_rec[slot];
+      rec.tag = p.req.tag;
+      rec.slot = slot;
+      rec.arrival = p.req.arrival;
+      rec.admitted = now();
+      rec.done = 0.0;
+      rec.status = RFI_OK;
+      // HIP calls run without the mutex: the completion callback takes it
+      lk.unlock();
+      int rc = launch(slot, p.req);
+      if (rc == RFI_OK && hipLaunchHostFunc(streams[slot], &rfi_server::on_done, &ctx[slot]) != hipSuccess)
+        rc = set_error(RFI_ERR_DEVICE, "hipLaunchHostFunc failed");
+      if (rc != RFI_OK) (void)hipStreamSynchronize(streams[slot]);
+      lk.lock();
+      if (rc != RFI_OK) {  // no callback was enqueued: complete the request here
+        rfi_completion r = slot_rec[slot];
+        r.status = rc;
+        r.done = now();
+        done.push_back(r);
+        slot_busy[slot] = false;
+        slot_plan[slot] = nullptr;
+        inflight_bytes -= p.bytes;
+        inflight -= 1;
+        outstanding -= 1;
+        stats.completed += 1;
+        stats.failed += 1;
+        cv_done.notify_all();
+      }
+    }
+    if (stop && outstanding == 0) break;
+    // sleep until something changed since this pass began, or the next arrival is due
+    auto changed = [this, seen] { return events != seen || (stop && outstanding == 0); };
+    if (!future.empty()) {
+      const auto wake = t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(future.begin()->first));
+      cv_sched.wait_until(lk, wake, changed);
+    } else {
+      cv_sched.wait(lk, changed);
+    }
+  }
+}
+
+extern "C" {
+
+int rfi_server_create(const rfi_server_config *cfg, rfi_server **out) {
+  if (out == nullptr) return set_error(RFI_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (cfg == nullptr) return set_error(RFI_ERR_INVALID_ARGUMENT, "cfg is NULL");
+  if (cfg->n_slots < 1 || cfg->n_slots > 64) return set_error(RFI_ERR_INVALID_ARGUMENT, "n_slots must be in 1..64");
+  if (cfg->hbm_budget == 0) return set_error(RFI_ERR_INVALID_ARGUMENT, "hbm_budget must be > 0");
+  if (cfg->device < 0) return set_error(RFI_ERR_INVALID_ARGUMENT, "device must be >= 0");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || cfg->device >= count)
+    return set_error(RFI_ERR_DEVICE, "device not available");
+  rfi_server *s = new (std::nothrow) rfi_server();
+  if (s == nullptr) return set_error(RFI_ERR_OUT_OF_MEMORY, "host allocation failed");
+  s->cfg = *cfg;
+  s->t0 = Clock::now();
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(cfg->device);
+  const int n = cfg->n_slots;
+  s->streams.assign(n, nullptr);
+  s->slot_busy.assign(n, false);
+  s->slot_plan.assign(n, nullptr);
+  s->slot_bytes.assign(n, 0);
+  s->slot_rec.assign(n, rfi_completion{});
+  s->ctx.resize(n);
+  for (int i = 0; i < n; ++i) {
+    s->ctx[i] = SlotCtx{s, i};
+    if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipStreamDestroy(s->streams[j]);
+      (void)hipSetDevice(prev);
+      delete s;
+      return set_error(RFI_ERR_DEVICE, "hipStreamCreateWithFlags failed");
+    }
+  }
+  (void)hipSetDevice(prev);
+  s->thread = std::thread([s] { s->run(); });
+  *out = s;
+  return RFI_OK;
+}
+
+double rfi_server_now(const rfi_server *srv) { return srv ? srv->now() : 0.0; }
+
+int rfi_server_submit(rfi_server *srv, const rfi_request *req) {
+  if (srv == nullptr || req == nullptr) return set_error(RFI_ERR_INVALID_ARGUMENT, "server and request must not be NULL");
+  if (req->plan == nullptr || req->vis == nullptr || req->avg == nullptr || req->weight == nullptr)
+    return set_error(RFI_ERR_INVALID_ARGUMENT, "plan, vis, avg and weight must not be NULL");
+  if (reinterpret_cast<uintptr_t>(req->vis) % 16 || reinterpret_cast<uintptr_t>(req->avg) % 16)
+    return set_error(RFI_ERR_INVALID_ARGUMENT, "vis and avg must be 16-byte aligned");
+  size_t bytes = 0;
+  if (rfi_plan_footprint(req->plan, &bytes) != RFI_OK) return set_error(RFI_ERR_INVALID_ARGUMENT, "bad plan");
+  if (bytes > srv->cfg.hbm_budget)
+    return set_error(RFI_ERR_INVALID_ARGUMENT, "request footprint exceeds the server's HBM budget");
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stop) return set_error(RFI_ERR_INVALID_ARGUMENT, "server is stopping");
+    Pending p{*req, (uint64_t)bytes, srv->seq++};
+    srv->future.emplace(req->arrival, p);
+    srv->outstanding += 1;
+    srv->stats.submitted += 1;
+    srv->events += 1;
+  }
+  srv->cv_sched.notify_one();
+  return RFI_OK;
+}
+
+int rfi_server_poll(rfi_server *srv, rfi_completion *out, int32_t max, int32_t *n_out, double timeout_s) {
+  if (srv == nullptr || n_out == nullptr || (out == nullptr && max > 0))
+    return set_error(RFI_ERR_INVALID_ARGUMENT, "server, out and n_out must not be NULL");
+  *n_out = 0;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  if (srv->done.empty() && timeout_s > 0)
+    srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [srv] { return !srv->done.empty(); });
+  int32_t n = 0;
+  while (n < max && !srv->done.empty()) {
+    out[n++] = srv->done.front();
+    srv->done.pop_front();
+  }
+  *n_out = n;
+  return RFI_OK;
+}
+
+int rfi_server_drain(rfi_server *srv, double timeout_s) {
+  if (srv == nullptr) return set_error(RFI_ERR_INVALID_ARGUMENT, "server is NULL");
+  std::unique_lock<std::mutex> lk(srv->mu);
+  const bool ok = srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [srv] { return srv->outstanding == 0; });
+  return ok ? RFI_OK : set_error(RFI_ERR_DEVICE, "drain timed out");
+}
+
+int rfi_server_get_stats(const rfi_server *srv, rfi_server_stats *out) {
+  if (srv == nullptr || out == nullptr) return set_error(RFI_ERR_INVALID_ARGUMENT, "server and out must not be NULL");
+  std::lock_guard<std::mutex> lk(const_cast<rfi_server *>(srv)->mu);
+  *out = srv->stats;
+  out->graphs = srv->n_graphs.load();
+  return RFI_OK;
+}
+
+int rfi_server_destroy(rfi_server *srv) {
+  if (srv == nullptr) return RFI_OK;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+    srv->events += 1;
+  }
+  srv->cv_sched.notify_one();
+  if (srv->thread.joinable()) srv->thread.join();
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(srv->cfg.device);
+  for (hipStream_t st : srv->streams) (void)hipStreamSynchronize(st);
+  for (auto &kv : srv->graphs) {
+    (void)hipGraphExecDestroy(kv.second.second);
+    (void)hipGraphDestroy(kv.second.first);
+  }
+  for (hipStream_t st : srv->streams) (void)hipStreamDestroy(st);
+  (void)hipSetDevice(prev);
+  delete srv;
+  return RFI_OK;
+}
+
+}  // extern "C"

@@ -43,6 +43,8 @@ EXPORTS = (
     "rfi_params_default", "rfi_plan_create", "rfi_screen", "rfi_destroy", "rfi_last_error",
     "rfi_plan_footprint", "rfi_state_bytes", "rfi_state_get", "rfi_state_set",
     "rfi_state_reset", "rfi_probe_sink_floats", "rfi_probe_read", "rfi_probe_copy",
+    "rfi_server_create", "rfi_server_now", "rfi_server_submit", "rfi_server_poll",
+    "rfi_server_drain", "rfi_server_get_stats", "rfi_server_destroy",
 )
 
 
@@ -74,6 +76,28 @@ class rfi_params(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rfi_server_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("n_slots", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_uint64), ("use_graphs", ctypes.c_int32)]
+
+
+class rfi_request(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("vis", ctypes.c_void_p), ("avg", ctypes.c_void_p),
+                ("weight", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("stats", ctypes.c_void_p),
+                ("arrival", ctypes.c_double), ("tag", ctypes.c_uint64)]
+
+
+class rfi_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("arrival", ctypes.c_double), ("admitted", ctypes.c_double), ("done", ctypes.c_double)]
+
+
+class rfi_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("peak_inflight_bytes", ctypes.c_uint64),
+                ("peak_inflight", ctypes.c_int32), ("graphs", ctypes.c_int32)]
 
 
 _lib = None
@@ -112,6 +136,14 @@ def load_library(path: str = LIB_PATH):
         "rfi_probe_sink_floats": (ctypes.c_size_t, [ctypes.c_size_t]),
         "rfi_probe_read": (ctypes.c_int, [vp, ctypes.c_size_t, vp, vp]),
         "rfi_probe_copy": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+        "rfi_server_create": (ctypes.c_int, [P(rfi_server_config), P(vp)]),
+        "rfi_server_now": (ctypes.c_double, [vp]),
+        "rfi_server_submit": (ctypes.c_int, [vp, P(rfi_request)]),
+        "rfi_server_poll": (ctypes.c_int, [vp, P(rfi_completion), ctypes.c_int32,
+                                           P(ctypes.c_int32), ctypes.c_double]),
+        "rfi_server_drain": (ctypes.c_int, [vp, ctypes.c_double]),
+        "rfi_server_get_stats": (ctypes.c_int, [vp, P(rfi_server_stats)]),
+        "rfi_server_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -307,3 +339,100 @@ def _numel(shape):
     for s in shape:
         n *= s
     return n
+
+
+# --------------------------------------------------------------------------- serving loop
+
+def rfi_server_create(n_slots: int = 16, hbm_budget: int = 200 << 30, device: int = 0,
+                      use_graphs: bool = True) -> int:
+    cfg = rfi_server_config(device=device, n_slots=n_slots, hbm_budget=hbm_budget,
+                            use_graphs=1 if use_graphs else 0)
+    h = ctypes.c_void_p()
+    _check(load_library().rfi_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def rfi_server_now(server: int) -> float:
+    return load_library().rfi_server_now(server)
+
+
+def rfi_server_submit(server: int, plan: int, vis, avg, weight, flags=None, stats=None,
+                      arrival: float = 0.0, tag: int = 0) -> None:
+    req = rfi_request(plan=plan, vis=_ptr(vis), avg=_ptr(avg), weight=_ptr(weight),
+                      flags=_ptr(flags), stats=_ptr(stats), arrival=arrival, tag=tag)
+    _check(load_library().rfi_server_submit(server, ctypes.byref(req)))
+
+
+def rfi_server_poll(server: int, max_n: int = 256, timeout: float = 0.0):
+    buf = (rfi_completion * max_n)()
+    n = ctypes.c_int32()
+    _check(load_library().rfi_server_poll(server, buf, max_n, ctypes.byref(n), timeout))
+    return [dict(tag=c.tag, status=c.status, slot=c.slot, arrival=c.arrival,
+                 admitted=c.admitted, done=c.done) for c in buf[:n.value]]
+
+
+def rfi_server_drain(server: int, timeout: float = 600.0) -> None:
+    _check(load_library().rfi_server_drain(server, timeout))
+
+
+def rfi_server_get_stats(server: int) -> dict:
+    st = rfi_server_stats()
+    _check(load_library().rfi_server_get_stats(server, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in st._fields_}
+
+
+def rfi_server_destroy(server: Optional[int]) -> None:
+    _check(load_library().rfi_server_destroy(server))
+
+
+class Server:
+    """Serving loop with tensor checks; keeps each in-flight request's tensors alive."""
+
+    def __init__(self, n_slots: int = 16, hbm_budget: int = 200 << 30, device: int = 0,
+                 use_graphs: bool = True):
+        self.handle = rfi_server_create(n_slots, hbm_budget, device, use_graphs)
+        self._live = {}
+
+    def now(self) -> float:
+        return rfi_server_now(self.handle)
+
+    def submit(self, plan: "Plan", vis, out: dict, arrival: Optional[float] = None, tag: int = 0):
+        import torch
+        plan._check_tensor("vis", vis, plan.vis_shape, plan.vis_dtype())
+        plan._check_tensor("avg", out["avg"], (plan.B, plan.C, 4, 2), torch.float32)
+        plan._check_tensor("weight", out["weight"], (plan.B, plan.C), torch.float32)
+        plan._check_tensor("flags", out.get("flags"), (plan.B, plan.C, plan.nW), torch.uint8)
+        plan._check_tensor("stats", out.get("stats"), (plan.B, plan.C, plan.nW, 3), torch.float32)
+        if tag in self._live:
+            raise ValueError(f"tag {tag} is already in flight")
+        self._live[tag] = (vis, out)
+        try:
+            rfi_server_submit(self.handle, plan.handle, vis, out["avg"], out["weight"], out.get("flags"),
+                              out.get("stats"), self.now() if arrival is None else arrival, tag)
+        except Exception:
+            del self._live[tag]
+            raise
+
+    def poll(self, max_n: int = 256, timeout: float = 0.0):
+        done = rfi_server_poll(self.handle, max_n, timeout)
+        for c in done:
+            self._live.pop(c["tag"], None)
+        return done
+
+    def drain(self, timeout: float = 600.0):
+        rfi_server_drain(self.handle, timeout)
+
+    def stats(self) -> dict:
+        return rfi_server_get_stats(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            rfi_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -36,7 +36,7 @@ __all__ = [
     "baseline_pairs", "n_baselines", "jones", "inr_to_amplitude", "Rfi",
     "Scene", "make_voltages", "correlate", "correlate_torch", "to_cf16",
     "scene_plain", "scene_fp32_baseline", "scene_mixed", "scene_null",
-    "scene_serving_array", "rfi_truth",
+    "scene_serving_array", "rfi_truth", "device_voltages", "serving_mix",
 ]
 
 
@@ -238,6 +238,36 @@ def correlate_torch(e_dev, out_dev, fmt: str = "cf32", chunk: int = 64):
     return out_dev
 
 
+def device_voltages(scene: Scene, device, seed_offset: int = 0):
+    """Station voltages e[N][C][T][2] (complex64) drawn directly on a torch device.
+
+    Same model as ``make_voltages`` (receiver noise, common sky, voltage-level RFI)
+    but with torch's device generator seeded from the scene, for arrays too large to
+    draw on the host quickly.  Not bit-identical to ``make_voltages``.
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(scene.seed) * 7919 + seed_offset)
+    N, C, T = scene.n_stations, scene.n_channels, scene.n_samples
+    std = float(np.sqrt(0.5))
+    e = torch.complex(torch.randn((N, C, T, 2), generator=g, device=device) * std,
+                      torch.randn((N, C, T, 2), generator=g, device=device) * std)
+    s = torch.complex(torch.randn((C, T, 2), generator=g, device=device) * std,
+                      torch.randn((C, T, 2), generator=g, device=device) * std)
+    e.mul_(float(np.sqrt(1.0 - scene.rho))).add_(s.unsqueeze(0), alpha=float(np.sqrt(scene.rho)))
+    rng = np.random.default_rng(scene.seed + seed_offset)
+    t = np.arange(T)
+    for src in scene.rfi:
+        A = inr_to_amplitude(src.inr_db)
+        env = np.ones(T) if src.envelope is None else src.envelope
+        sig = A * (env * np.exp(2j * np.pi * src.f0 * t))[:, None] * jones(src.theta, src.chi)[None, :]
+        rot = np.exp(1j * rng.uniform(0.0, 2 * np.pi, size=N))[:, None, None]
+        add = torch.from_numpy((rot * sig[None]).astype(np.complex64)).to(device)   # [N, T, 2]
+        for c in src.channels:
+            e[:, c] += add
+    return e
+
+
 def to_cf16(vis: np.ndarray) -> np.ndarray:
     """complex64 [..., 4] -> float16 [..., 4, 2] (re, im), round to nearest even."""
     return np.ascontiguousarray(vis).view(np.float32).reshape(vis.shape + (2,)).astype(np.float16)
@@ -322,3 +352,18 @@ def scene_serving_array(n_stations: int, n_channels: int, seed: int,
                         n_samples: int = 3072) -> Scene:
     """One array of the serving mix: like the FP32 baseline scene at another size."""
     return scene_fp32_baseline(seed, n_stations, n_channels, n_samples)
+
+
+def serving_mix(seed: int = 4, n_arrays: int = 16, max_total_bytes: float = 96e9,
+                n_samples: int = 3072):
+    """The serving workload: arrays of 12, 24, 48 or 64 stations with 16-256 channels,
+    drawn per seed; redrawn (deterministically) until their complex-half inputs fit
+    ``max_total_bytes`` together.  Returns a list of scenes."""
+    rng = np.random.default_rng(seed + 5_000_003)
+    while True:
+        Ns = rng.choice([12, 24, 48, 64], size=n_arrays)
+        Cs = rng.choice([16, 32, 64, 128, 256], size=n_arrays)
+        total = sum(n_baselines(int(n)) * int(c) * n_samples * 16 for n, c in zip(Ns, Cs))
+        if total <= max_total_bytes:
+            break
+    return [scene_serving_array(int(n), int(c), seed * 100 + i, n_samples) for i, (n, c) in enumerate(zip(Ns, Cs))]

@@ -1,0 +1,143 @@
+"""The serving loop: continuous batching with HBM admission; results alone == results in the mix."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import TOL_F32, compare, make_params, run_gpu, to_device
+
+pytestmark = pytest.mark.gpu
+
+ARRAYS = [(3, 8), (5, 16), (2, 32), (4, 4), (6, 8)]      # (stations, channels)
+T, M, N_INT = 1024, 64, 3
+
+
+def _params(N, C):
+    B = N * (N + 1) // 2
+    return make_params(B, C, T, M, "cf16", d=2.2, s_low=0.5, s_high=1.6, gamma=0.3,
+                       options=oracle.OPT_ADAPTIVE, n_warm=32, kappa_sk=3.0, kappa_ds=3.0)
+
+
+def _data():
+    """Integrations of every array, pre-staged on the device (complex half)."""
+    out = {}
+    for a, (N, C) in enumerate(ARRAYS):
+        for k in range(N_INT):
+            env = synth.pulse_train(T, 128, 20, 7 * k + a)
+            sc = synth.Scene(N, C, T, seed=1000 * a + k, rho=0.1,
+                             rfi=[synth.Rfi([C // 2], 10.0, 0.5, 0.2, env, f0=0.1)])
+            vis = synth.to_cf16(synth.correlate(synth.make_voltages(sc)))
+            out[a, k] = (vis, to_device(vis, "cf16"))
+    return out
+
+
+def _host(res):
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in res.items()}
+
+
+def test_results_alone_equal_results_in_the_mix():
+    import torch
+    from paper_2412_14775_amd import rfi
+    data = _data()
+    # alone: one array at a time, integrations in order, default stream
+    alone = {}
+    for a, (N, C) in enumerate(ARRAYS):
+        plan = rfi.Plan(_params(N, C)[1])
+        for k in range(N_INT):
+            out = plan.alloc_outputs(flags=True, stats=True)
+            plan.screen(data[a, k][1], out["avg"], out["weight"], out["flags"], out["stats"])
+            torch.cuda.synchronize()
+            alone[a, k] = _host(out)
+        plan.close()
+    # in the mix: fresh plans, every request submitted with random arrival times
+    plans = [rfi.Plan(_params(N, C)[1]) for (N, C) in ARRAYS]
+    srv = rfi.Server(n_slots=4, hbm_budget=1 << 36)
+    rng = np.random.default_rng(3)
+    t0 = srv.now() + 0.05
+    outs = {}
+    for k in range(N_INT):
+        for a in rng.permutation(len(ARRAYS)):
+            outs[a, k] = plans[a].alloc_outputs(flags=True, stats=True)
+            srv.submit(plans[a], data[a, k][1], outs[a, k], arrival=t0 + 0.01 * k + rng.uniform(0, 0.01),
+                       tag=int(100 * a + k))
+    srv.drain(60)
+    done = srv.poll(1000)
+    st = srv.stats()
+    srv.close()
+    assert len(done) == len(ARRAYS) * N_INT and all(c["status"] == 0 for c in done)
+    assert st["peak_inflight"] > 1, "requests never overlapped"
+    assert st["graphs"] == len(done)               # one graph per (plan, buffer set)
+    for c in done:
+        assert c["arrival"] <= c["admitted"] <= c["done"]
+    order = {}
+    for c in sorted(done, key=lambda c: c["done"]):
+        a, k = divmod(c["tag"], 100)
+        assert order.get(a, -1) == k - 1, "integrations of one array completed out of order"
+        order[a] = k
+    for key, ref in alone.items():
+        got = _host(outs[key])
+        for name in ("avg", "weight", "flags", "stats"):
+            assert np.array_equal(got[name], ref[name], equal_nan=True), (key, name)
+    for p in plans:
+        p.close()
+    # the first integration of one array against the oracle (plan thresholds: state still cold)
+    op, _ = _params(*ARRAYS[1])
+    gpu = run_gpu_from_host(alone[1, 0])
+    compare(gpu, data[1, 0][0], op, TOL_F32, label="served integration vs oracle")
+
+
+def run_gpu_from_host(h):
+    g = {"avg": h["avg"][..., 0].astype(np.float64) + 1j * h["avg"][..., 1], "weight": h["weight"],
+         "flags": h["flags"], "stats32": h["stats"]}
+    g["tau"], g["r_re"], g["r_im"] = (h["stats"][..., k].astype(np.float64) for k in range(3))
+    return g
+
+
+def test_admission_respects_the_hbm_budget():
+    import torch
+    from paper_2412_14775_amd import rfi
+    N, C = 5, 16
+    plans = [rfi.Plan(_params(N, C)[1]) for _ in range(6)]
+    fp = plans[0].footprint()
+    srv = rfi.Server(n_slots=8, hbm_budget=int(2.5 * fp))
+    vis = to_device(np.zeros((N * (N + 1) // 2, C, T, 4, 2), np.float16), "cf16")
+    outs = []
+    for i, p in enumerate(plans):
+        outs.append(p.alloc_outputs())
+        srv.submit(p, vis, outs[-1], arrival=0.0, tag=i)
+    srv.drain(60)
+    st = srv.stats()
+    assert st["completed"] == 6 and st["failed"] == 0
+    assert st["peak_inflight_bytes"] <= int(2.5 * fp)
+    assert st["peak_inflight"] <= 2
+    big = rfi.Server(n_slots=2, hbm_budget=fp - 1)
+    with pytest.raises(rfi.RfiError):
+        big.submit(plans[0], vis, outs[0], tag=99)
+    big.close()
+    srv.close()
+    torch.cuda.synchronize()
+    for p in plans:
+        p.close()
+
+
+def test_direct_launch_mode_matches_graph_mode():
+    import torch
+    from paper_2412_14775_amd import rfi
+    N, C = 4, 8
+    _, rp = _params(N, C)
+    vis = synth.to_cf16(synth.correlate(synth.make_voltages(synth.Scene(N, C, T, seed=5))))
+    dev = to_device(vis, "cf16")
+    res = []
+    for graphs in (True, False):
+        plan = rfi.Plan(rp)
+        srv = rfi.Server(n_slots=2, use_graphs=graphs)
+        out = plan.alloc_outputs(flags=True, stats=True)
+        srv.submit(plan, dev, out, tag=1)
+        srv.drain(30)
+        assert srv.poll(10)[0]["status"] == 0
+        srv.close()
+        torch.cuda.synchronize()
+        res.append(_host(out))
+        plan.close()
+    for name in ("avg", "weight", "flags", "stats"):
+        assert np.array_equal(res[0][name], res[1][name], equal_nan=True), name
