@@ -170,6 +170,41 @@ def stored_traffic(digest: str, per_launch_alg: float):
     return t.get("cf32_bytes_per_launch")
 
 
+def tf_window_form(steps: int, warmup: int):
+    """The paper's own window shape, 10 time samples x 2 channels (W = 20), on a 48-station,
+    64-channel integration of 3000 samples (T divisible by 10), complex64 and complex half."""
+    import torch
+    from paper_2412_14775_amd import rfi
+    dev = torch.device("cuda:0")
+    sc = synth.scene_fp32_baseline(SEED, N_STATIONS, N_CHANNELS, 3000)
+    e = synth.device_voltages(sc, dev)
+    B, C, T = sc.n_baselines, sc.n_channels, sc.n_samples
+    vis32 = torch.empty((B, C, T, 4, 2), dtype=torch.float32, device=dev)
+    synth.correlate_torch(e, vis32, "cf32")
+    del e
+    stream = torch.cuda.Stream(device=dev)
+    res = {"window": "10 x 2", "samples": T}
+    for name, fmt, sb in (("cf32", rfi.RFI_VIS_CF32, 32), ("cf16", rfi.RFI_VIS_CF16, 16)):
+        vis = vis32 if fmt == rfi.RFI_VIS_CF32 else vis32.to(torch.float16)
+        params = rfi.rfi_params_default(n_stations=N_STATIONS, n_baselines=B, n_channels=C,
+                                        n_samples=T, block_m=10, block_f=2, vis_format=fmt,
+                                        sk_d=2.2, sk_low=0.42, sk_high=2.0, ds_gamma=0.40)
+        plan = rfi.Plan(params)
+        outs = plan.alloc_outputs(flags=True, stats=False)
+        with torch.cuda.stream(stream):
+            per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup)
+        plan.close()
+        alg = B * C * (T * sb + 36) + B * (C // 2) * (T // 10)
+        res[name] = {"samples_per_s": B * C * T * steps / (total_ms * 1e-3),
+                     "kernel_ms_mean": float(per.mean()),
+                     "achieved_GBs": alg / (per.mean() * 1e-3) / 1e9,
+                     "hbm_frac": alg / (per.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del vis
+    del vis32
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving(seconds: float, rate: float):
     """Serving form: 16 arrays (12-64 stations, 16-256 channels, M = 64, complex half,
     adaptive thresholds), inputs pre-staged in HBM; Poisson arrivals at `rate` per second in
@@ -306,6 +341,7 @@ def main(argv=None):
     copy_calibration(vis32, stream)
     del vis32, vis16
     torch.cuda.empty_cache()
+    tf = tf_window_form(max(10, args.steps // 4), max(2, args.warmup // 4))
     serve = serving(args.serving_seconds, 16.0) if args.serving_seconds > 0 else None
 
     f32 = forms["cf32"]
@@ -338,6 +374,7 @@ def main(argv=None):
                                                "achieved_GBs", "hbm_frac")},
         "cf16_over_cf32": forms["cf16"]["samples_per_s"] / f32["samples_per_s"],
         "read_probe_GBs": probe,
+        "tf_window": tf,
         "serving": serve,
         "flagged_frac": f32["flagged_frac"],
         "kernel_source_digest": digest,

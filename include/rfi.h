@@ -87,17 +87,18 @@ typedef struct rfi_params {
   float kappa_sk;      /* ADAPTIVE: s_low/high = mean_tau -/+ kappa_sk * sd_tau, kappa >= 0 */
   float kappa_ds;      /* ADAPTIVE: gamma_re/im = mean_r + kappa_ds * sd_r                  */
   int32_t n_warm;      /* ADAPTIVE: windows a stream must have seen before its own thresholds */
-  int32_t block_f;     /* F, channels per window (time x frequency window); 1 = time only  */
+  int32_t block_f;     /* F, adjacent channels per window: 1 (time only), 2 or 4 (time x  */
+                       /* frequency window of M x F samples, Sections 3.2 and 4.1)          */
 } rfi_params;
 
 typedef struct rfi_plan rfi_plan; /* opaque */
 
-/* Fill *p with defaults: eps = 2^-23, d = 1, s_low = 0.5, s_high = 2, gamma = 0.4,
+/* Fill *p with defaults: eps = 2^-23, d = 1, s_low = 0.5, s_high = 2, gamma = 0.4, M = 64,
  * block_f = 1, kappa_sk = kappa_ds = 3, n_warm = 0, CF32, options 0; sizes zero. */
 void rfi_params_default(rfi_params *p);
 
 /*
- * Validate *params, choose the kernel for (vis_format, block_m), and allocate
+ * Validate *params, choose the kernel for (vis_format, block_m, block_f), and allocate
  * the plan's device state on `device` (the ADAPTIVE state, zeroed; nothing
  * otherwise).  On success *out receives the plan; on error *out is NULL.
  * Errors: INVALID_ARGUMENT (shape or threshold rules above), DEVICE, OUT_OF_MEMORY.
@@ -111,8 +112,11 @@ int rfi_plan_create(const rfi_params *params, int device, rfi_plan **out);
  *   avg    [B][C][4][2] float32: flag-masked time average of each correlation
  *          over unflagged samples; 0 when every window is flagged.       (write)
  *   weight [B][C] float32: unflagged fraction of the T samples.           (write)
- *   flags  [B][C][T/M] uint8 RFI_FLAG_* bits per window, or NULL.         (write)
- *   stats  [B][C][T/M][3] float32 (tau, r_re, r_im) per window, or NULL.  (write)
+ *   flags  [B][C/F][T/M] uint8 RFI_FLAG_* bits per window, or NULL.       (write)
+ *   stats  [B][C/F][T/M][3] float32 (tau, r_re, r_im) per window, or NULL.(write)
+ * A window is M time samples of F adjacent channels (channels f*F .. f*F+F-1 of
+ * one baseline); W = M F enters tau and r, and a flag removes the window's
+ * samples of all F channels from their averages.
  *   hip_stream: a hipStream_t (NULL = default stream).
  * With RFI_OPT_ADAPTIVE the thresholds of each stream come from the plan's
  * state, which this call then updates from the unflagged windows; calls on one
@@ -138,7 +142,7 @@ const char *rfi_last_error(void);
 int rfi_plan_footprint(const rfi_plan *plan, size_t *bytes);
 
 /*
- * ADAPTIVE state, per stream b*C + c, 32 bytes:
+ * ADAPTIVE state, per channel group b*(C/F) + c/F (per stream when F = 1), 32 bytes:
  *   uint32 n; float mean[3]; float m2[3]; uint32 reserved
  * (statistics in the order tau, r_re, r_im; m2 = sum of squared deviations).
  * rfi_state_get / rfi_state_set copy the whole state to / from host memory
@@ -162,6 +166,34 @@ int rfi_probe_read(const void *src, size_t bytes, float *sink, void *hip_stream)
 /* Plain device copy of `bytes` (multiple of 16): a kernel of known traffic used to
  * calibrate hardware byte counters. */
 int rfi_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Hyperparameters (Section 2.3): the thresholds follow from a desired false-alarm
+ * probability, and small windows need fine-tuning on RFI-free data.  Host functions, no
+ * device access.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Exact mean, variance and skewness of tau for i.i.d. Gamma(d)-distributed |I| in a window
+ * of W samples (the null model of the SK estimator; mean 1, variance
+ * 2d(d+1)W^2 Gamma(Wd+2) / ((W-1) Gamma(Wd+4))), from moments of the Dirichlet distribution
+ * of |I_i| / S1.  Errors: INVALID_ARGUMENT (W < 2, d <= 0, NULL output). */
+int rfi_sk_null_moments(int32_t W, float d, double *mean, double *var, double *skew);
+
+/* Thresholds for false-alarm probabilities pfa_sk (two-sided, pfa/2 per side) and pfa_ds:
+ * sk_low / sk_high = Cornish-Fisher quantiles of tau from its exact null moments; ds_gamma =
+ * sqrt(chi2_3^-1(1 - pfa_ds) / (3W)) (3 W r^2 tends to chi-square with 3 degrees of freedom
+ * for isotropic directions).  Approximate for small W (tau's lower tail especially); refine
+ * with rfi_calibrate_from_stats.  W is the window size M F. */
+int rfi_thresholds_from_pfa(int32_t W, float d, double pfa_sk, double pfa_ds, float *sk_low, float *sk_high,
+                            float *ds_gamma);
+
+/* Calibrate on the statistics of RFI-free data: `stats` is host memory [n_windows][3]
+ * (tau, r_re, r_im) as rfi_screen writes them with sk_d = d_used.  d_cal makes the mean of tau
+ * 1; sk_low / sk_high are the pfa_sk/2 and 1 - pfa_sk/2 quantiles of tau recomputed with
+ * d_cal; ds_gamma is the 1 - pfa_ds quantile of the pooled r_re and nonzero r_im.  Non-finite
+ * statistics are ignored.  Errors: INVALID_ARGUMENT (NULL, bad probabilities, degenerate data). */
+int rfi_calibrate_from_stats(const float *stats, size_t n_windows, int32_t W, float d_used, double pfa_sk,
+                             double pfa_ds, float *d_cal, float *sk_low, float *sk_high, float *ds_gamma);
 
 /* ------------------------------------------------------------------------------------------
  * Serving: a persistent request loop that screens integrations of many arrays as they

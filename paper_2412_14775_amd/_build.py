@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librfi.so")
-SOURCES = ["screen.hip", "api.hip", "serve.hip"]
+SOURCES = ["screen.hip", "api.hip", "serve.hip", "calibrate.cpp"]
 
 
 def hipcc() -> str:

@@ -17,6 +17,7 @@ struct rfi_plan {
   rfi_params p;
   int device;
   int64_t n_streams;
+  int64_t n_groups;  // channel groups: n_streams / block_f
   int32_t nW;
   int32_t n_seg;
   size_t sample_bytes;
@@ -97,7 +98,10 @@ int validate(const rfi_params *p) {
       return fail(RFI_ERR_INVALID_ARGUMENT, "kappa_sk and kappa_ds must be finite and >= 0");
     if (p->n_warm < 0) return fail(RFI_ERR_INVALID_ARGUMENT, "n_warm must be >= 0");
   }
-  if (p->block_f != 1) return fail(RFI_ERR_UNSUPPORTED, "block_f > 1 (time x frequency windows) is not built");
+  if (p->block_f != 1 && p->block_f != 2 && p->block_f != 4)
+    return fail(RFI_ERR_UNSUPPORTED, "block_f must be 1, 2 or 4 (got %d)", p->block_f);
+  if ((int64_t)p->block_f * p->n_samples * sb >= (int64_t)1 << 31)
+    return fail(RFI_ERR_INVALID_ARGUMENT, "block_f * n_samples * bytes per sample must be < 2^31");
   return RFI_OK;
 }
 
@@ -105,6 +109,7 @@ int validate(const rfi_params *p) {
 // (window-aligned segments) so that small arrays still fill the GPU.
 int choose_segments(const rfi_params &p, int64_t n_streams) {
   int n_seg = 1;
+  if (p.block_f != 1) return 1;
   const int64_t target_waves = 64 * 1024;
   while (n_seg < rfi::kWavesPerBlock && n_streams * n_seg < target_waves &&
          p.n_samples % (2 * n_seg * p.block_m) == 0 && p.n_samples / (2 * n_seg) >= 256 &&
@@ -158,6 +163,7 @@ int rfi_plan_create(const rfi_params *params, int device, rfi_plan **out) {
   plan->p = *params;
   plan->device = device;
   plan->n_streams = (int64_t)params->n_baselines * params->n_channels;
+  plan->n_groups = plan->n_streams / params->block_f;
   plan->nW = params->n_samples / params->block_m;
   plan->sample_bytes = params->vis_format == RFI_VIS_CF32 ? 32 : 16;
   plan->n_seg = choose_segments(*params, plan->n_streams);
@@ -167,7 +173,7 @@ int rfi_plan_create(const rfi_params *params, int device, rfi_plan **out) {
       delete plan;
       return hip_fail(g.error(), "hipSetDevice");
     }
-    plan->state_bytes = (size_t)plan->n_streams * sizeof(rfi::StateRec);
+    plan->state_bytes = (size_t)plan->n_groups * sizeof(rfi::StateRec);
     e = hipMalloc(&plan->state, plan->state_bytes);
     if (e != hipSuccess) {
       delete plan;
@@ -202,17 +208,19 @@ int rfi_screen(rfi_plan *plan, const void *vis, float *avg, float *weight, uint8
   a.flags = flags;
   a.stats = stats;
   a.state = static_cast<uint32_t *>(plan->state);
-  a.n_streams = plan->n_streams;
+  a.n_groups = plan->n_groups;
+  a.F = p.block_f;
   a.T = p.n_samples;
   a.M = p.block_m;
   a.nW = plan->nW;
   a.n_seg = plan->n_seg;
   a.seg_samples = p.n_samples / plan->n_seg;
   a.seg_windows = a.seg_samples / p.block_m;
-  const double M = p.block_m;
-  a.pre = (float)((M * (double)p.sk_d + 1.0) / (M - 1.0));
-  a.Mf = (float)M;
-  a.invM = (float)(1.0 / M);
+  const double W = (double)p.block_m * p.block_f;
+  a.pre = (float)((W * (double)p.sk_d + 1.0) / (W - 1.0));
+  a.Wf = (float)W;
+  a.invW = (float)(1.0 / W);
+  a.Mt = (float)p.block_m;
   a.eps = p.eps;
   a.s_low = p.sk_low;
   a.s_high = p.sk_high;
@@ -248,7 +256,7 @@ int rfi_plan_footprint(const rfi_plan *plan, size_t *bytes) {
   if (plan == nullptr || bytes == nullptr) return fail(RFI_ERR_INVALID_ARGUMENT, "plan and bytes must not be NULL");
   const size_t S = (size_t)plan->n_streams;
   const size_t vis = S * (size_t)plan->p.n_samples * plan->sample_bytes;
-  const size_t out = S * (8 * sizeof(float) + sizeof(float) + (size_t)plan->nW);
+  const size_t out = S * (8 * sizeof(float) + sizeof(float)) + (size_t)plan->n_groups * plan->nW;
   *bytes = plan->state_bytes + vis + out;
   return ok();
 }

@@ -14,17 +14,19 @@ struct ScreenArgs {
   float *weight;        // [streams]
   uint8_t *flags;       // [streams][nW] or null
   float *stats;         // [streams][nW][3] or null
-  uint32_t *state;      // [streams][8] adaptive state or null
-  int64_t n_streams;    // B * C
+  uint32_t *state;      // [groups][8] adaptive state or null
+  int64_t n_groups;     // B * C / F: channel groups (= streams when F = 1)
+  int32_t F;            // channels per window (1, 2 or 4)
   int32_t T;            // samples per stream
-  int32_t M;            // window length
-  int32_t nW;           // windows per stream = T / M
-  int32_t n_seg;        // waves per stream (1, 2 or 4)
+  int32_t M;            // window length in time samples
+  int32_t nW;           // windows per group = T / M
+  int32_t n_seg;        // waves per group (1, 2 or 4)
   int32_t seg_samples;  // samples per wave segment = T / n_seg
   int32_t seg_windows;  // windows per wave segment = seg_samples / M
-  float pre;            // (M d + 1) / (M - 1)
-  float Mf;             // M as float
-  float invM;           // 1 / M
+  float pre;            // (W d + 1) / (W - 1), W = M F
+  float Wf;             // W as float
+  float invW;           // 1 / W
+  float Mt;             // M as float (time samples of a window, per channel)
   float eps;
   float s_low, s_high, gamma;
   float kappa_sk, kappa_ds;

@@ -166,22 +166,25 @@ __device__ __forceinline__ void accumulate_sample(float ws[8], float wr[8], cons
   for (int k = 0; k < 8; ++k) wr[k] += x[k];
 }
 
-// Per-stream running results of a wave.
+// Per-stream running results of a wave.  A window covers F adjacent channels
+// of one baseline (F = 1: a single channel), each with its own masked sum.
+template <int F>
 struct StreamAcc {
-  float sum[8];  // masked raw sums (lane partials)
-  float kept;    // clean samples (lane partial)
-  Moments mom;   // statistics of clean windows (adaptive state)
+  float sum[F][8];  // masked raw sums per channel (lane partials)
+  float kept;       // clean time samples (lane partial; the same for the F channels)
+  Moments mom;      // statistics of clean windows (adaptive state)
 };
 
 // Statistics and flag of one window from its totals; flag / stats written by
 // the window's leader lane; raw partials folded in when the window is clean.
+template <int F>
 __device__ __forceinline__ void finish_window(const ScreenArgs &a, const Thresholds &th,
-                                              const float tot[8], const float wr[8],
+                                              const float tot[8], const float (*wr)[8],
                                               int64_t out_index, bool valid, bool leader,
-                                              StreamAcc &acc) {
-  const float tau = a.pre * (a.Mf * tot[1] / (tot[0] * tot[0] + a.eps) - 1.0f);
-  const float r_re = sqrtf(tot[2] * tot[2] + tot[3] * tot[3] + tot[4] * tot[4]) * a.invM;
-  const float r_im = sqrtf(tot[5] * tot[5] + tot[6] * tot[6] + tot[7] * tot[7]) * a.invM;
+                                              StreamAcc<F> &acc) {
+  const float tau = a.pre * (a.Wf * tot[1] / (tot[0] * tot[0] + a.eps) - 1.0f);
+  const float r_re = sqrtf(tot[2] * tot[2] + tot[3] * tot[3] + tot[4] * tot[4]) * a.invW;
+  const float r_im = sqrtf(tot[5] * tot[5] + tot[6] * tot[6] + tot[7] * tot[7]) * a.invW;
   uint32_t bits = (!(tau >= th.s_low) ? 1u : 0u) | (tau > th.s_high ? 2u : 0u) |
                   (!(r_re <= th.g_re) ? 4u : 0u) | (!(r_im <= th.g_im) ? 8u : 0u);
   if (a.options & 1u) bits &= ~3u;
@@ -189,11 +192,13 @@ __device__ __forceinline__ void finish_window(const ScreenArgs &a, const Thresho
   const bool clean = valid && bits == 0u;
   if (clean) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc.sum[k] += wr[k];
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc.sum[f][k] += wr[f][k];
   }
   if (valid && leader) {
     if (clean) {
-      acc.kept += a.Mf;
+      acc.kept += a.Mt;
       if (a.state != nullptr) moments_push(acc.mom, tau, r_re, r_im);
     }
     if (a.flags != nullptr) a.flags[out_index] = (uint8_t)bits;
@@ -206,13 +211,18 @@ __device__ __forceinline__ void finish_window(const ScreenArgs &a, const Thresho
   }
 }
 
-// End of a stream: reduce the wave's partials, combine the segments of the
-// stream (waves of one block), write average, weight and the adaptive state.
-__device__ __forceinline__ void finish_stream(const ScreenArgs &a, StreamAcc &acc, int64_t stream,
+constexpr int kXfer = 4 * 8 + 8;  // per-wave LDS record: sums of up to 4 channels, kept, moments
+
+// End of a stream group: reduce the wave's partials, combine the segments
+// (waves of one block), write average, weight and the adaptive state.
+template <int F>
+__device__ __forceinline__ void finish_stream(const ScreenArgs &a, StreamAcc<F> &acc, int64_t group,
                                               int seg, bool active, int wave, int lane,
-                                              float (*xfer)[16]) {
+                                              float (*xfer)[kXfer]) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) acc.sum[k] = group_sum<64>(acc.sum[k]);
+  for (int f = 0; f < F; ++f)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc.sum[f][k] = group_sum<64>(acc.sum[f][k]);
   acc.kept = group_sum<64>(acc.kept);
   if (a.state != nullptr) {
 #pragma unroll
@@ -220,15 +230,18 @@ __device__ __forceinline__ void finish_stream(const ScreenArgs &a, StreamAcc &ac
       acc.mom = moments_merge(acc.mom, moments_shfl_xor(acc.mom, mask));
   }
   if (a.n_seg > 1) {  // uniform over the block
+    constexpr int o = 8 * F;
     if (lane == 0) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) xfer[wave][k] = acc.sum[k];
-      xfer[wave][8] = acc.kept;
-      xfer[wave][9] = acc.mom.n;
+      for (int f = 0; f < F; ++f)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) xfer[wave][8 * f + k] = acc.sum[f][k];
+      xfer[wave][o] = acc.kept;
+      xfer[wave][o + 1] = acc.mom.n;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        xfer[wave][10 + k] = acc.mom.m[k];
-        xfer[wave][13 + k] = acc.mom.s[k];
+        xfer[wave][o + 2 + k] = acc.mom.m[k];
+        xfer[wave][o + 5 + k] = acc.mom.s[k];
       }
     }
     __syncthreads();
@@ -236,14 +249,16 @@ __device__ __forceinline__ void finish_stream(const ScreenArgs &a, StreamAcc &ac
       for (int s = 1; s < a.n_seg; ++s) {
         const float *x = xfer[wave + s];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc.sum[k] += x[k];
-        acc.kept += x[8];
+        for (int f = 0; f < F; ++f)
+#pragma unroll
+          for (int k = 0; k < 8; ++k) acc.sum[f][k] += x[8 * f + k];
+        acc.kept += x[o];
         Moments b;
-        b.n = x[9];
+        b.n = x[o + 1];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          b.m[k] = x[10 + k];
-          b.s[k] = x[13 + k];
+          b.m[k] = x[o + 2 + k];
+          b.s[k] = x[o + 5 + k];
         }
         acc.mom = moments_merge(acc.mom, b);
       }
@@ -251,12 +266,16 @@ __device__ __forceinline__ void finish_stream(const ScreenArgs &a, StreamAcc &ac
   }
   if (!active || seg != 0 || lane != 0) return;
   const float inv = acc.kept > 0.0f ? 1.0f / acc.kept : 0.0f;
-  f32x4 *out = reinterpret_cast<f32x4 *>(a.avg + stream * 8);
-  out[0] = f32x4{acc.sum[0] * inv, acc.sum[1] * inv, acc.sum[2] * inv, acc.sum[3] * inv};
-  out[1] = f32x4{acc.sum[4] * inv, acc.sum[5] * inv, acc.sum[6] * inv, acc.sum[7] * inv};
-  a.weight[stream] = acc.kept * a.invT;
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    const int64_t stream = group * F + f;
+    f32x4 *out = reinterpret_cast<f32x4 *>(a.avg + stream * 8);
+    out[0] = f32x4{acc.sum[f][0] * inv, acc.sum[f][1] * inv, acc.sum[f][2] * inv, acc.sum[f][3] * inv};
+    out[1] = f32x4{acc.sum[f][4] * inv, acc.sum[f][5] * inv, acc.sum[f][6] * inv, acc.sum[f][7] * inv};
+    a.weight[stream] = acc.kept * a.invT;
+  }
   if (a.state != nullptr && acc.mom.n > 0.0f) {
-    StateRec *st = reinterpret_cast<StateRec *>(a.state) + stream;
+    StateRec *st = reinterpret_cast<StateRec *>(a.state) + group;
     StateRec r = *st;
     Moments old;
     old.n = (float)r.n;
@@ -288,16 +307,16 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
   constexpr int IPW = M > SPI ? M / SPI : 1;    // steps per window
 
   __shared__ u32x4 tile[kWavesPerBlock][kTilePieces];
-  __shared__ float xfer[kWavesPerBlock][16];
+  __shared__ float xfer[kWavesPerBlock][kXfer];
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
   const int64_t unit = (int64_t)blockIdx.x * kWavesPerBlock + wave;
   const int64_t stream = unit / a.n_seg;
   const int seg = (int)(unit - stream * a.n_seg);
-  const bool active = stream < a.n_streams;
+  const bool active = stream < a.n_groups;
 
-  StreamAcc acc{};
+  StreamAcc<1> acc{};
   if (active) {
     const Thresholds th = stream_thresholds(a, stream);
     const uint8_t *base = a.vis + (stream * a.T + (int64_t)seg * a.seg_samples) * SB;
@@ -316,7 +335,7 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
                        rsrc, (unsigned)(step * SPI * SB + (i * kWave + lane) * 16), 0, kLoadStreaming));
     };
 
-    float ws[8] = {}, wr[8] = {};
+    float ws[8] = {}, wr[1][8] = {};
     issue(0);
     for (int step = 0; step < n_steps; ++step) {
       wave_lds_order();
@@ -338,13 +357,13 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
 #pragma unroll
           for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
         }
-        accumulate_sample(ws, wr, x, a.eps);
+        accumulate_sample(ws, wr[0], x, a.eps);
         if constexpr (LOCAL) {
           if ((j + 1) % M == 0) {
             const int w = (step * SPI + lane * K) / M + j / M;
-            finish_window(a, th, ws, wr, out_base + w, w < a.seg_windows, true, acc);
+            finish_window<1>(a, th, ws, wr, out_base + w, w < a.seg_windows, true, acc);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) ws[k] = wr[k] = 0.0f;
+            for (int k = 0; k < 8; ++k) ws[k] = wr[0][k] = 0.0f;
           }
         }
       }
@@ -354,59 +373,63 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
 #pragma unroll
           for (int k = 0; k < 8; ++k) tot[k] = group_sum<LPW>(ws[k]);
           const int w = ((step + 1 - IPW) * SPI + lane * K) / M;
-          finish_window(a, th, tot, wr, out_base + w, w < a.seg_windows, lane % LPW == 0, acc);
+          finish_window<1>(a, th, tot, wr, out_base + w, w < a.seg_windows, lane % LPW == 0, acc);
 #pragma unroll
-          for (int k = 0; k < 8; ++k) ws[k] = wr[k] = 0.0f;
+          for (int k = 0; k < 8; ++k) ws[k] = wr[0][k] = 0.0f;
         }
       }
     }
   }
-  finish_stream(a, acc, stream, seg, active, wave, lane, xfer);
+  finish_stream<1>(a, acc, stream, seg, active, wave, lane, xfer);
 }
 
-// Any window length (M >= 2, including M that is not a power of two): one
-// wave per stream, one lane per window, samples read directly.  Slower than
-// the tiled kernel; kept for window lengths it does not cover.
-template <int FMT>
+// Any window length (M >= 2, including M that is not a power of two) and
+// time x frequency windows of F = 1, 2 or 4 adjacent channels: one wave per
+// channel group, one lane per window, samples read directly.  Slower than the
+// tiled kernel; used for the shapes the tiled kernel does not cover.
+template <int FMT, int F>
 __global__ void __launch_bounds__(kBlock) screen_generic(const ScreenArgs a) {
   constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
-  __shared__ float xfer[kWavesPerBlock][16];
+  __shared__ float xfer[kWavesPerBlock][kXfer];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
-  const int64_t stream = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-  const bool active = stream < a.n_streams;
-  StreamAcc acc{};
+  const int64_t group = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const bool active = group < a.n_groups;
+  StreamAcc<F> acc{};
   if (active) {
-    const Thresholds th = stream_thresholds(a, stream);
-    const uint8_t *base = a.vis + stream * a.T * SB;
+    const Thresholds th = stream_thresholds(a, group);
+    const uint8_t *base = a.vis + group * F * (int64_t)a.T * SB;
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint8_t *>(base), (short)0, a.T * SB, kRsrcWord3);
+        const_cast<uint8_t *>(base), (short)0, F * a.T * SB, kRsrcWord3);
     for (int w = lane; w < a.nW; w += kWave) {
-      float ws[8] = {}, wr[8] = {};
-      for (int t = 0; t < a.M; ++t) {
-        const unsigned off = (unsigned)((w * a.M + t) * SB);
-        float x[8];
-        if constexpr (FMT == FMT_CF32) {
-          const f32x4 lo = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
-          const f32x4 hi = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + 16, 0, kLoadStreaming));
-          x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
-          x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
-        } else {
-          const f16x8 h = __builtin_bit_cast(f16x8, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
+      float ws[8] = {}, wr[F][8] = {};
 #pragma unroll
-          for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
+      for (int f = 0; f < F; ++f) {
+        for (int t = 0; t < a.M; ++t) {
+          const unsigned off = (unsigned)((f * a.T + w * a.M + t) * SB);
+          float x[8];
+          if constexpr (FMT == FMT_CF32) {
+            const f32x4 lo = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
+            const f32x4 hi = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + 16, 0, kLoadStreaming));
+            x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
+            x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
+          } else {
+            const f16x8 h = __builtin_bit_cast(f16x8, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
+          }
+          accumulate_sample(ws, wr[f], x, a.eps);
         }
-        accumulate_sample(ws, wr, x, a.eps);
       }
-      finish_window(a, th, ws, wr, stream * a.nW + w, true, true, acc);
+      finish_window<F>(a, th, ws, wr, group * a.nW + w, true, true, acc);
     }
   }
-  finish_stream(a, acc, stream, 0, active, wave, lane, xfer);
+  finish_stream<F>(a, acc, group, 0, active, wave, lane, xfer);
 }
 
 template <int FMT, int LOG2M>
 hipError_t launch_tiled(const ScreenArgs &a, hipStream_t stream) {
-  const int64_t units = a.n_streams * a.n_seg;
+  const int64_t units = a.n_groups * a.n_seg;
   const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
   hipLaunchKernelGGL((screen_tiled<FMT, LOG2M>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, a);
   return hipGetLastError();
@@ -433,8 +456,14 @@ hipError_t dispatch_tiled(int log2m, const ScreenArgs &a, hipStream_t stream) {
 
 template <int FMT>
 hipError_t launch_generic(const ScreenArgs &a, hipStream_t stream) {
-  const int64_t blocks = (a.n_streams + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL((screen_generic<FMT>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, a);
+  const int64_t blocks = (a.n_groups + kWavesPerBlock - 1) / kWavesPerBlock;
+  const dim3 grid((unsigned)blocks), block(kBlock);
+  switch (a.F) {
+    case 1: hipLaunchKernelGGL((screen_generic<FMT, 1>), grid, block, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((screen_generic<FMT, 2>), grid, block, 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((screen_generic<FMT, 4>), grid, block, 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -482,7 +511,7 @@ bool tiled_supports(int M) {
 
 hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream) {
   const int l = ilog2_exact(a.M);
-  const bool tiled = l >= 1 && l <= kMaxTiledLog2M;
+  const bool tiled = a.F == 1 && l >= 1 && l <= kMaxTiledLog2M;
   if (fmt == FMT_CF32) return tiled ? dispatch_tiled<FMT_CF32>(l, a, stream) : launch_generic<FMT_CF32>(a, stream);
   if (fmt == FMT_CF16) return tiled ? dispatch_tiled<FMT_CF16>(l, a, stream) : launch_generic<FMT_CF16>(a, stream);
   return hipErrorInvalidValue;

@@ -45,6 +45,7 @@ EXPORTS = (
     "rfi_state_reset", "rfi_probe_sink_floats", "rfi_probe_read", "rfi_probe_copy",
     "rfi_server_create", "rfi_server_now", "rfi_server_submit", "rfi_server_poll",
     "rfi_server_drain", "rfi_server_get_stats", "rfi_server_destroy",
+    "rfi_sk_null_moments", "rfi_thresholds_from_pfa", "rfi_calibrate_from_stats",
 )
 
 
@@ -144,6 +145,14 @@ def load_library(path: str = LIB_PATH):
         "rfi_server_drain": (ctypes.c_int, [vp, ctypes.c_double]),
         "rfi_server_get_stats": (ctypes.c_int, [vp, P(rfi_server_stats)]),
         "rfi_server_destroy": (ctypes.c_int, [vp]),
+        "rfi_sk_null_moments": (ctypes.c_int, [ctypes.c_int32, ctypes.c_float, P(ctypes.c_double),
+                                               P(ctypes.c_double), P(ctypes.c_double)]),
+        "rfi_thresholds_from_pfa": (ctypes.c_int, [ctypes.c_int32, ctypes.c_float, ctypes.c_double,
+                                                   ctypes.c_double, P(ctypes.c_float), P(ctypes.c_float),
+                                                   P(ctypes.c_float)]),
+        "rfi_calibrate_from_stats": (ctypes.c_int, [vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_float,
+                                                    ctypes.c_double, ctypes.c_double, P(ctypes.c_float),
+                                                    P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -267,6 +276,8 @@ class Plan:
         self.handle = rfi_plan_create(params, device)
         p = params
         self.B, self.C, self.T, self.M = p.n_baselines, p.n_channels, p.n_samples, p.block_m
+        self.F = p.block_f
+        self.G = self.C // self.F           # channel groups (windows span F channels)
         self.nW = self.T // self.M
         self.cf16 = p.vis_format == RFI_VIS_CF16
 
@@ -297,8 +308,8 @@ class Plan:
         d = self.device
         out = dict(avg=torch.empty((self.B, self.C, 4, 2), dtype=torch.float32, device=d),
                    weight=torch.empty((self.B, self.C), dtype=torch.float32, device=d),
-                   flags=torch.empty((self.B, self.C, self.nW), dtype=torch.uint8, device=d) if flags else None,
-                   stats=torch.empty((self.B, self.C, self.nW, 3), dtype=torch.float32, device=d) if stats else None)
+                   flags=torch.empty((self.B, self.G, self.nW), dtype=torch.uint8, device=d) if flags else None,
+                   stats=torch.empty((self.B, self.G, self.nW, 3), dtype=torch.float32, device=d) if stats else None)
         return out
 
     def _check_tensor(self, name, t, shape, dtype):
@@ -321,15 +332,15 @@ class Plan:
         self._check_tensor("vis", vis, self.vis_shape, self.vis_dtype())
         self._check_tensor("avg", avg, (self.B, self.C, 4, 2), torch.float32)
         self._check_tensor("weight", weight, (self.B, self.C), torch.float32)
-        self._check_tensor("flags", flags, (self.B, self.C, self.nW), torch.uint8)
-        self._check_tensor("stats", stats, (self.B, self.C, self.nW, 3), torch.float32)
+        self._check_tensor("flags", flags, (self.B, self.G, self.nW), torch.uint8)
+        self._check_tensor("stats", stats, (self.B, self.G, self.nW, 3), torch.float32)
         rfi_screen(self.handle, vis, avg, weight, flags, stats, stream)
 
     def state(self):
-        """Adaptive state as a numpy structured array [B][C] (n, mean[3], m2[3])."""
+        """Adaptive state as a numpy structured array [B][C/F] (n, mean[3], m2[3])."""
         import numpy as np
         dt = np.dtype([("n", np.uint32), ("mean", np.float32, 3), ("m2", np.float32, 3), ("reserved", np.uint32)])
-        a = np.zeros((self.B, self.C), dt)
+        a = np.zeros((self.B, self.G), dt)
         rfi_state_get(self.handle, a.view(np.uint8))
         return a
 
@@ -401,8 +412,8 @@ class Server:
         plan._check_tensor("vis", vis, plan.vis_shape, plan.vis_dtype())
         plan._check_tensor("avg", out["avg"], (plan.B, plan.C, 4, 2), torch.float32)
         plan._check_tensor("weight", out["weight"], (plan.B, plan.C), torch.float32)
-        plan._check_tensor("flags", out.get("flags"), (plan.B, plan.C, plan.nW), torch.uint8)
-        plan._check_tensor("stats", out.get("stats"), (plan.B, plan.C, plan.nW, 3), torch.float32)
+        plan._check_tensor("flags", out.get("flags"), (plan.B, plan.G, plan.nW), torch.uint8)
+        plan._check_tensor("stats", out.get("stats"), (plan.B, plan.G, plan.nW, 3), torch.float32)
         if tag in self._live:
             raise ValueError(f"tag {tag} is already in flight")
         self._live[tag] = (vis, out)
@@ -436,3 +447,45 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------- hyperparameters
+
+def rfi_sk_null_moments(W: int, d: float):
+    m, v, s = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().rfi_sk_null_moments(W, d, ctypes.byref(m), ctypes.byref(v), ctypes.byref(s)))
+    return m.value, v.value, s.value
+
+
+def rfi_thresholds_from_pfa(W: int, d: float, pfa_sk: float = 0.05, pfa_ds: float = 0.05) -> dict:
+    lo, hi, g = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+    _check(load_library().rfi_thresholds_from_pfa(W, d, pfa_sk, pfa_ds, ctypes.byref(lo), ctypes.byref(hi),
+                                                  ctypes.byref(g)))
+    return dict(sk_low=lo.value, sk_high=hi.value, ds_gamma=g.value)
+
+
+def rfi_calibrate_from_stats(stats, W: int, d_used: float, pfa_sk: float = 0.05, pfa_ds: float = 0.05) -> dict:
+    """stats: host float32 array [..., 3] of (tau, r_re, r_im) from RFI-free data."""
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(stats, np.float32).reshape(-1, 3))
+    d, lo, hi, g = ctypes.c_float(), ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+    _check(load_library().rfi_calibrate_from_stats(a.ctypes.data, a.shape[0], W, d_used, pfa_sk, pfa_ds,
+                                                   ctypes.byref(d), ctypes.byref(lo), ctypes.byref(hi),
+                                                   ctypes.byref(g)))
+    return dict(sk_d=d.value, sk_low=lo.value, sk_high=hi.value, ds_gamma=g.value)
+
+
+def calibrate_on_null(params: rfi_params, vis, pfa_sk: float = 0.05, pfa_ds: float = 0.05,
+                      device: int = 0) -> dict:
+    """Screen RFI-free visibilities ``vis`` (device tensor) with ``params`` on the GPU and
+    calibrate d and the thresholds from the kernel's statistics (fine-tuning, Section 2.3)."""
+    import torch
+    plan = Plan(params, device)
+    try:
+        out = plan.alloc_outputs(flags=False, stats=True)
+        plan.screen(vis, out["avg"], out["weight"], None, out["stats"])
+        torch.cuda.synchronize()
+        st = out["stats"].cpu().numpy()
+    finally:
+        plan.close()
+    return rfi_calibrate_from_stats(st, params.block_m * params.block_f, params.sk_d, pfa_sk, pfa_ds)

@@ -32,7 +32,8 @@ def make_params(B, C, T, M, fmt="cf32", **kw):
         n_stations=N, n_baselines=B, n_channels=C, n_samples=T, block_m=M,
         vis_format=rfi.RFI_VIS_CF16 if fmt == "cf16" else rfi.RFI_VIS_CF32,
         sk_d=op.d, sk_low=op.s_low, sk_high=op.s_high, ds_gamma=op.gamma, eps=op.eps,
-        options=op.options, kappa_sk=op.kappa_sk, kappa_ds=op.kappa_ds, n_warm=op.n_warm)
+        options=op.options, kappa_sk=op.kappa_sk, kappa_ds=op.kappa_ds, n_warm=op.n_warm,
+        block_f=op.F)
     return op, rp
 
 
@@ -95,10 +96,10 @@ def flags_from_stats32(st32, th, options):
     return bits.astype(np.uint8)
 
 
-def avg_scale(vis, flags, M):
+def avg_scale(vis, flags, M, F=1):
     """Mean magnitude of each correlation over the kept samples (the condition of the sum)."""
     v = oracle.as_complex128(vis)
-    keep = np.repeat(np.asarray(flags) == 0, M, axis=-1)
+    keep = np.repeat(np.repeat(np.asarray(flags) == 0, F, axis=-2), M, axis=-1)
     n = np.maximum(keep.sum(-1), 1)
     return np.where(keep[..., None], np.abs(v), 0.0).sum(-2) / n[..., None]
 
@@ -131,7 +132,7 @@ def compare(gpu, vis_for_oracle, op: "oracle.Params", tol, thresholds=None, ref=
             assert np.array_equal(own, gpu["flags"]), f"{label}: flags differ from the rule applied to the kernel's own statistics"
         # conditional parity of the average: the oracle average with the GPU's flags
         avg_c, w_c = oracle.masked_average(vis_for_oracle, gpu["flags"], op.M, op.F)
-        scale = avg_scale(vis_for_oracle, gpu["flags"], op.M)
+        scale = avg_scale(vis_for_oracle, gpu["flags"], op.M, op.F)
         e = np.abs(gpu["avg"] - avg_c) / np.maximum(scale, 1e-30)
         rep["max_err_avg"] = float(e.max()) if e.size else 0.0
         assert e.max(initial=0.0) <= tol, f"{label}: avg max rel err {e.max():.3g} > {tol}"

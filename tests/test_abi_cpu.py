@@ -91,7 +91,7 @@ def test_null_arguments():
 
 
 def test_unsupported_block_f_reports_unsupported():
-    p = rfi.rfi_params_default(**{**GOOD, "block_f": 2})
+    p = rfi.rfi_params_default(**{**GOOD, "block_f": 8})
     with pytest.raises(rfi.RfiError) as ei:
         rfi.rfi_plan_create(p)
     assert ei.value.code == rfi.RFI_ERR_UNSUPPORTED

@@ -16,15 +16,15 @@ def _integration(i, N=2, C=8, T=1024):
     return synth.correlate(synth.make_voltages(sc))
 
 
-@pytest.mark.parametrize("fmt,M", [("cf32", 16), ("cf16", 64), ("cf32", 20)])
-def test_adaptive_thresholds_follow_oracle_state(fmt, M):
+@pytest.mark.parametrize("fmt,M,F", [("cf32", 16, 1), ("cf16", 64, 1), ("cf32", 20, 1), ("cf16", 10, 2)])
+def test_adaptive_thresholds_follow_oracle_state(fmt, M, F):
     from paper_2412_14775_amd import rfi
-    B, C, T = 3, 8, 1280 if M == 20 else 1024
+    B, C, T = 3, 8, 1280 if M in (10, 20) else 1024
     kw = dict(d=2.1, s_low=0.2, s_high=2.6, gamma=0.5, kappa_sk=3.0, kappa_ds=3.0,
-              n_warm=80, options=oracle.OPT_ADAPTIVE)
+              n_warm=80, options=oracle.OPT_ADAPTIVE, F=F)
     op, rp = make_params(B, C, T, M, fmt, **kw)
     plan = rfi.Plan(rp)
-    state = oracle.AdaptiveState((B, C))
+    state = oracle.AdaptiveState((B, C // F))
     warm_seen = False
     for i in range(6):
         vis = _integration(i, T=T)

@@ -51,11 +51,12 @@ def screen_both(vis, M, fmt="cf32", stats=True, **kw):
 def check_cf16(vis, M, label, **kw):
     """Complex-half storage: arithmetic error against the oracle on the same FP16 bytes
     (1e-5, every M) and total error against the oracle on the original complex64 input
-    (3e-3).  The total bound is asserted for M >= 16: for M < 16 the storage rounding
-    alone, amplified by (Md+1)/(M-1), can exceed it whatever the kernel does."""
+    (3e-3).  The total bound is asserted for windows of W >= 16 samples: for W < 16 the
+    storage rounding alone, amplified by (Wd+1)/(W-1), can exceed it whatever the kernel does."""
     op, gpu = screen_both(vis, M, "cf16", **kw)
     rep_a = compare(gpu, synth.to_cf16(vis), op, TOL_F32, label=label + " (fp16 input)")
-    rep_t = compare(gpu, vis, op, TOL_F16_TOTAL, label=label + " (original input)") if M >= 16 else None
+    W = M * kw.get("F", 1)
+    rep_t = compare(gpu, vis, op, TOL_F16_TOTAL, label=label + " (original input)") if W >= 16 else None
     return rep_a, rep_t
 
 
@@ -110,6 +111,29 @@ def test_few_long_streams_split_over_waves(fmt, M, T):
         compare(gpu, vis, op, TOL_F32, label=f"segmented cf32 M={M} T={T}")
     else:
         check_cf16(vis, M, f"segmented cf16 M={M} T={T}", **thresholds_for(M))
+
+
+# ----------------------------------------------------------------------------- time x frequency windows
+
+@pytest.mark.parametrize("fmt", ["cf32", "cf16"])
+@pytest.mark.parametrize("M,F,C,T", [(10, 2, 8, 400), (5, 4, 8, 300), (16, 2, 6, 512), (20, 1, 4, 400),
+                                     (64, 4, 4, 3072)])
+def test_time_frequency_windows(fmt, M, F, C, T):
+    """Windows of M time samples x F adjacent channels (the paper's 10 x 2 and 5 x 4 shapes)."""
+    vis = scene_vis(3, C, T, seed=31 + M * F, rfi_channels=(1, 2), duty=(50, 12))
+    th = thresholds_for(M * F)
+    if fmt == "cf32":
+        op, gpu = screen_both(vis, M, F=F, **th)
+        rep = compare(gpu, vis, op, TOL_F32, label=f"cf32 {M}x{F}")
+    else:
+        rep, _ = check_cf16(vis, M, f"cf16 {M}x{F}", F=F, **th)
+    assert gpu_flag_shape_ok(vis, M, F)
+    print(f"{fmt} {M}x{F}", rep)
+
+
+def gpu_flag_shape_ok(vis, M, F):
+    B, C, T, _ = vis.shape
+    return C % F == 0 and T % M == 0
 
 
 # ----------------------------------------------------------------------------- edge cases
