@@ -76,7 +76,9 @@ class Rfi:
     theta,chi : polarisation state (Jones vector j(theta, chi)); ignored if ``unpolarized``
     envelope  : 0/1 time envelope of length T (None = always on)
     f0        : tone frequency in cycles per sample
-    unpolarized : draw an independent random 2-vector per sample instead of a fixed j
+    unpolarized : a constant-modulus wave whose polarisation is a random unit 2-vector drawn
+                  independently per sample (no preferred direction)
+    pol_frac  : fraction of the RFI power in the fixed state j; the rest is unpolarised as above
     """
     channels: Sequence[int]
     inr_db: float
@@ -85,6 +87,7 @@ class Rfi:
     envelope: Optional[np.ndarray] = None
     f0: float = 0.05
     unpolarized: bool = False
+    pol_frac: float = 1.0
 
 
 def pulse_train(T: int, period: int, on: int, phase: int) -> np.ndarray:
@@ -157,12 +160,13 @@ def make_voltages(scene: Scene) -> np.ndarray:
         tone = np.exp(1j * (2 * np.pi * src.f0 * t))                        # [T]
         rot = np.exp(1j * phi)[:, None, None]                                # [N, 1, 1]
         for c in src.channels:
-            if src.unpolarized:
-                # an independent random 2-vector per sample, E|j|^2 = 1
-                jv = _cn(rng, (T, 2)).astype(np.complex128) * np.sqrt(0.5)
-                sig = A * (g * tone)[:, None] * jv                           # [T, 2]
-            else:
-                sig = A * (g * tone)[:, None] * jones(src.theta, src.chi)[None, :]
+            p = 0.0 if src.unpolarized else src.pol_frac
+            jv = np.sqrt(p) * jones(src.theta, src.chi)[None, :] * np.ones((T, 1))
+            if p < 1.0:
+                u = _cn(rng, (T, 2)).astype(np.complex128)
+                u /= np.linalg.norm(u, axis=1, keepdims=True)                # random unit 2-vector
+                jv = jv + np.sqrt(1.0 - p) * u
+            sig = A * (g * tone)[:, None] * jv                               # [T, 2]
             e[:, c] += (rot * sig[None]).astype(np.complex64)
     return e
 

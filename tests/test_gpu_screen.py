@@ -117,7 +117,7 @@ def test_few_long_streams_split_over_waves(fmt, M, T):
 
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
 @pytest.mark.parametrize("M,F,C,T", [(10, 2, 8, 400), (5, 4, 8, 300), (16, 2, 6, 512), (20, 1, 4, 400),
-                                     (64, 4, 4, 3072)])
+                                     (64, 4, 8, 3072)])
 def test_time_frequency_windows(fmt, M, F, C, T):
     """Windows of M time samples x F adjacent channels (the paper's 10 x 2 and 5 x 4 shapes)."""
     vis = scene_vis(3, C, T, seed=31 + M * F, rfi_channels=(1, 2), duty=(50, 12))
