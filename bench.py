@@ -184,22 +184,28 @@ def tf_window_form(steps: int, warmup: int):
     del e
     stream = torch.cuda.Stream(device=dev)
     res = {"window": "10 x 2", "samples": T}
-    for name, fmt, sb in (("cf32", rfi.RFI_VIS_CF32, 32), ("cf16", rfi.RFI_VIS_CF16, 16)):
+    flags = {}
+    for name, fmt, sb, opt in (("cf32", rfi.RFI_VIS_CF32, 32, 0), ("cf16", rfi.RFI_VIS_CF16, 16, 0),
+                               ("cf32_paper_mixed", rfi.RFI_VIS_CF32, 32, rfi.RFI_OPT_PAPER_MIXED)):
         vis = vis32 if fmt == rfi.RFI_VIS_CF32 else vis32.to(torch.float16)
         params = rfi.rfi_params_default(n_stations=N_STATIONS, n_baselines=B, n_channels=C,
-                                        n_samples=T, block_m=10, block_f=2, vis_format=fmt,
+                                        n_samples=T, block_m=10, block_f=2, vis_format=fmt, options=opt,
                                         sk_d=2.2, sk_low=0.42, sk_high=2.0, ds_gamma=0.40)
         plan = rfi.Plan(params)
         outs = plan.alloc_outputs(flags=True, stats=False)
         with torch.cuda.stream(stream):
             per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup)
         plan.close()
+        flags[name] = outs["flags"].clone()
         alg = B * C * (T * sb + 36) + B * (C // 2) * (T // 10)
         res[name] = {"samples_per_s": B * C * T * steps / (total_ms * 1e-3),
                      "kernel_ms_mean": float(per.mean()),
                      "achieved_GBs": alg / (per.mean() * 1e-3) / 1e9,
                      "hbm_frac": alg / (per.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del vis
+    res["paper_mixed_flag_disagreement_vs_cf32"] = float(
+        (flags["cf32_paper_mixed"] != flags["cf32"]).float().mean().item())
+    res["cf16_flag_disagreement_vs_cf32"] = float((flags["cf16"] != flags["cf32"]).float().mean().item())
     del vis32
     torch.cuda.empty_cache()
     return res

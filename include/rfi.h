@@ -56,7 +56,11 @@ typedef enum rfi_vis_format {
 enum {
   RFI_OPT_NO_SK = 1u,   /* do not apply the spectral-kurtosis test (bits 0-1 cleared)  */
   RFI_OPT_NO_DS = 2u,   /* do not apply the directional test (bits 2-3 cleared)        */
-  RFI_OPT_ADAPTIVE = 4u /* per-stream thresholds from running null statistics, below    */
+  RFI_OPT_ADAPTIVE = 4u, /* per-stream thresholds from running null statistics, below   */
+  RFI_OPT_PAPER_MIXED = 8u /* the paper's trained mixed precision (Tables 3-4): unit-vector  */
+                           /* sums, their squares, r and the SK ratio in FP16 (binary16     */
+                           /* rounding per operation), the rest FP32; complex64 storage and */
+                           /* M = K S with K <= 8, S a power of two, F S <= 64 only         */
 };
 
 /* Flag bits written per window.  A window is flagged when any bit is set. */

@@ -35,8 +35,9 @@ running mean/variance.  The adaptive-threshold extension is pinned only
 against NumPy's own mean/variance of the same windows ("parity unpinned" with
 respect to the paper, which gives no formula for it).
 """
+from .mixed import mixed_window_stats, screen_mixed  # noqa: F401
 from .screen import (  # noqa: F401
-    SK_LOW, SK_HIGH, DS_RE, DS_IM, OPT_NO_SK, OPT_NO_DS, OPT_ADAPTIVE,
+    SK_LOW, SK_HIGH, DS_RE, DS_IM, OPT_NO_SK, OPT_NO_DS, OPT_ADAPTIVE, OPT_PAPER_MIXED,
     Params, as_complex128, stokes, sk_tau, ds_r, flag_bits, window_view,
     screen, masked_average, AdaptiveState, screen_adaptive,
 )

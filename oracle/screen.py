@@ -41,7 +41,7 @@ from typing import Optional
 import numpy as np
 
 SK_LOW, SK_HIGH, DS_RE, DS_IM = 1, 2, 4, 8
-OPT_NO_SK, OPT_NO_DS, OPT_ADAPTIVE = 1, 2, 4
+OPT_NO_SK, OPT_NO_DS, OPT_ADAPTIVE, OPT_PAPER_MIXED = 1, 2, 4, 8
 
 EPS_DEFAULT = 2.0 ** -23
 

@@ -91,7 +91,7 @@ int validate(const rfi_params *p) {
   if (!(p->ds_gamma >= 0.0f && p->ds_gamma <= 1.0f))
     return fail(RFI_ERR_INVALID_ARGUMENT, "ds_gamma must be in [0, 1] (got %g)", p->ds_gamma);
   if (!(finite(p->eps) && p->eps >= 0.0f)) return fail(RFI_ERR_INVALID_ARGUMENT, "eps must be finite and >= 0");
-  if (p->options & ~(uint32_t)(RFI_OPT_NO_SK | RFI_OPT_NO_DS | RFI_OPT_ADAPTIVE))
+  if (p->options & ~(uint32_t)(RFI_OPT_NO_SK | RFI_OPT_NO_DS | RFI_OPT_ADAPTIVE | RFI_OPT_PAPER_MIXED))
     return fail(RFI_ERR_INVALID_ARGUMENT, "unknown option bits 0x%x", p->options);
   if (p->options & RFI_OPT_ADAPTIVE) {
     if (!(finite(p->kappa_sk) && p->kappa_sk >= 0.0f && finite(p->kappa_ds) && p->kappa_ds >= 0.0f))
@@ -102,6 +102,10 @@ int validate(const rfi_params *p) {
     return fail(RFI_ERR_UNSUPPORTED, "block_f must be 1, 2 or 4 (got %d)", p->block_f);
   if ((int64_t)p->block_f * p->n_samples * sb >= (int64_t)1 << 31)
     return fail(RFI_ERR_INVALID_ARGUMENT, "block_f * n_samples * bytes per sample must be < 2^31");
+  if ((p->options & RFI_OPT_PAPER_MIXED) &&
+      (p->vis_format != RFI_VIS_CF32 || rfi::windows_samples_per_lane(p->block_m, p->block_f) == 0))
+    return fail(RFI_ERR_UNSUPPORTED,
+                "RFI_OPT_PAPER_MIXED needs complex64 storage and a window M = K S (K <= 8, S a power of two, F S <= 64)");
   return RFI_OK;
 }
 
@@ -109,7 +113,7 @@ int validate(const rfi_params *p) {
 // (window-aligned segments) so that small arrays still fill the GPU.
 int choose_segments(const rfi_params &p, int64_t n_streams) {
   int n_seg = 1;
-  if (p.block_f != 1) return 1;
+  if (p.block_f != 1 || (p.options & RFI_OPT_PAPER_MIXED)) return 1;
   const int64_t target_waves = 64 * 1024;
   while (n_seg < rfi::kWavesPerBlock && n_streams * n_seg < target_waves &&
          p.n_samples % (2 * n_seg * p.block_m) == 0 && p.n_samples / (2 * n_seg) >= 256 &&

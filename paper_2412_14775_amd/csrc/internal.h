@@ -45,6 +45,7 @@ struct StateRec {
 static_assert(sizeof(StateRec) == 32, "state record is 32 bytes");
 
 enum : int { FMT_CF32 = 0, FMT_CF16 = 1 };
+constexpr uint32_t kOptPaperMixed = 8u;  // RFI_OPT_PAPER_MIXED
 
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
@@ -56,6 +57,8 @@ hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream);
 // Samples per lane per iteration of the tiled kernel for a format (4 for CF32, 8 for CF16).
 int tiled_samples_per_lane(int fmt);
 bool tiled_supports(int M);
+// Samples per lane of the windowed kernel for (M, F), or 0 when it does not apply.
+int windows_samples_per_lane(int M, int F);
 
 // Records the thread's last error (read back by rfi_last_error) and returns `code`.
 int set_error(int code, const char *fmt, ...);

@@ -177,14 +177,22 @@ struct StreamAcc {
 
 // Statistics and flag of one window from its totals; flag / stats written by
 // the window's leader lane; raw partials folded in when the window is clean.
-template <int F>
+__device__ __forceinline__ void mixed_statistics(const ScreenArgs &a, const float tot[8], float &tau, float &r_re,
+                                                 float &r_im);
+
+template <int F, bool MIXED = false>
 __device__ __forceinline__ void finish_window(const ScreenArgs &a, const Thresholds &th,
                                               const float tot[8], const float (*wr)[8],
                                               int64_t out_index, bool valid, bool leader,
                                               StreamAcc<F> &acc) {
-  const float tau = a.pre * (a.Wf * tot[1] / (tot[0] * tot[0] + a.eps) - 1.0f);
-  const float r_re = sqrtf(tot[2] * tot[2] + tot[3] * tot[3] + tot[4] * tot[4]) * a.invW;
-  const float r_im = sqrtf(tot[5] * tot[5] + tot[6] * tot[6] + tot[7] * tot[7]) * a.invW;
+  float tau, r_re, r_im;
+  if constexpr (MIXED) {
+    mixed_statistics(a, tot, tau, r_re, r_im);
+  } else {
+    tau = a.pre * (a.Wf * tot[1] / (tot[0] * tot[0] + a.eps) - 1.0f);
+    r_re = sqrtf(tot[2] * tot[2] + tot[3] * tot[3] + tot[4] * tot[4]) * a.invW;
+    r_im = sqrtf(tot[5] * tot[5] + tot[6] * tot[6] + tot[7] * tot[7]) * a.invW;
+  }
   uint32_t bits = (!(tau >= th.s_low) ? 1u : 0u) | (tau > th.s_high ? 2u : 0u) |
                   (!(r_re <= th.g_re) ? 4u : 0u) | (!(r_im <= th.g_im) ? 8u : 0u);
   if (a.options & 1u) bits &= ~3u;
@@ -383,6 +391,210 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
   finish_stream<1>(a, acc, stream, seg, active, wave, lane, xfer);
 }
 
+// ----------------------------------------------------------------------------- paper's mixed precision
+// Tables 3-4: per-sample groups and the SK moments in FP32; the sums of the unit
+// vectors, their squares, r and its comparison, and the SK ratio and its
+// comparison in FP16 (every FP16 operation rounds its result to binary16; FP32
+// inputs are converted first).
+
+__device__ __forceinline__ float round16(float x) { return (float)(_Float16)x; }
+
+// As accumulate_sample, but the unit-vector sums (Table 2 group 4) accumulate in FP16.
+__device__ __forceinline__ void accumulate_sample_mixed(float ws[8], float wr[8], const float x[8], float eps) {
+  const float Ir = x[0] + x[6], Ii = x[1] + x[7];
+  const float Qr = x[0] - x[6], Qi = x[1] - x[7];
+  const float Ur = x[2] + x[4], Ui = x[3] + x[5];
+  const float Vr = x[5] - x[3], Vi = x[2] - x[4];
+  const float y = Ir * Ir + Ii * Ii;
+  ws[0] += hw_sqrt(y);
+  ws[1] += y;
+  const float rr = hw_rcp(hw_sqrt(Qr * Qr + Ur * Ur + Vr * Vr) + eps);
+  const float ri = hw_rcp(hw_sqrt(Qi * Qi + Ui * Ui + Vi * Vi) + eps);
+  ws[2] = round16(ws[2] + round16(Qr * rr));
+  ws[3] = round16(ws[3] + round16(Ur * rr));
+  ws[4] = round16(ws[4] + round16(Vr * rr));
+  ws[5] = round16(ws[5] + round16(Qi * ri));
+  ws[6] = round16(ws[6] + round16(Ui * ri));
+  ws[7] = round16(ws[7] + round16(Vi * ri));
+#pragma unroll
+  for (int k = 0; k < 8; ++k) wr[k] += x[k];
+}
+
+// Group sum whose additions round to binary16 (operands are binary16 values).
+__device__ __forceinline__ float group_sum16_rt(float v, int L) {
+  if (L >= 2) v = round16(v + dpp_mov<0xB1>(v));
+  if (L >= 4) v = round16(v + dpp_mov<0x4E>(v));
+  if (L >= 8) v = round16(v + dpp_mov<0x141>(v));
+  if (L >= 16) v = round16(v + dpp_mov<0x140>(v));
+  if (L >= 32) v = round16(v + __shfl_xor(v, 16));
+  if (L >= 64) v = round16(v + __shfl_xor(v, 32));
+  return v;
+}
+
+// tau, r_re, r_im from window totals in the mixed precision.
+__device__ __forceinline__ void mixed_statistics(const ScreenArgs &a, const float tot[8], float &tau, float &r_re,
+                                                 float &r_im) {
+  const float s12 = tot[0] * tot[0];                                   // group 6, FP32
+  const float num = round16(round16(a.Wf) * round16(tot[1]));          // group 7, FP16
+  const float den = round16(round16(s12) + 0.0009765625f);             //   eps = 2^-10
+  const float ratio = round16(num / den);
+  tau = round16(round16(a.pre) * round16(ratio - 1.0f));
+  auto r16 = [&](float q, float u, float v) {
+    float sq = round16(round16(q * q) + round16(u * u));               // group 5, FP16
+    sq = round16(sq + round16(v * v));
+    return round16(round16(sqrtf(sq)) / round16(a.Wf));                // group 6, FP16
+  };
+  r_re = r16(tot[2], tot[3], tot[4]);
+  r_im = r16(tot[5], tot[6], tot[7]);
+}
+
+// Sum over aligned groups of L lanes for a run-time power of two L (uniform branches).
+__device__ __forceinline__ float group_sum_rt(float v, int L) {
+  if (L >= 2) v += dpp_mov<0xB1>(v);
+  if (L >= 4) v += dpp_mov<0x4E>(v);
+  if (L >= 8) v += dpp_mov<0x141>(v);
+  if (L >= 16) v += dpp_mov<0x140>(v);
+  if (L >= 32) v += __shfl_xor(v, 16);
+  if (L >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Windows of M = K S time samples x F channels, K <= 8, L = F S <= 64 lanes per
+// window (any M with such a factorisation, and every F > 1 shape the tiled kernel
+// does not take).  One wave per channel group.  Lane l = (j L + f S + s) owns the
+// K consecutive samples s of channel f of window j of the step, so a lane stays
+// on one channel and keeps one masked sum.  A step covers 64 / L windows: for
+// each channel a contiguous run of 64 K / F samples, loaded coalesced
+// (channel-major) into the wave's LDS tile and read back per lane.
+template <int FMT, int K, int F, bool MIXED>
+__global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
+  constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
+  constexpr int PPS = SB / 16;                  // 16-byte pieces per sample
+  constexpr int P = K * PPS;                    // pieces per lane per step
+  constexpr int CH_PIECES = kWave * P / F;      // pieces of one channel per step
+  constexpr int CH_SAMPLES = kWave * K / F;     // samples of one channel per step
+  __shared__ u32x4 tile[kWavesPerBlock][kWave * P];
+
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int64_t group = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const bool active = group < a.n_groups;
+  const int S = a.M / K;                        // lanes per channel of a window
+  const int L = F * S;                          // lanes per window
+  const int j = lane / L, f = (lane / S) % F, s = lane % S;
+  const int wps = kWave / L;                    // windows per step
+
+  float acc[8] = {};
+  float kept = 0.0f;
+  Moments mom{};
+  if (active) {
+    const Thresholds th = stream_thresholds(a, group);
+    const uint8_t *base = a.vis + group * F * (int64_t)a.T * SB;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t *>(base), (short)0, F * a.T * SB, kRsrcWord3);
+    const int n_steps = (a.nW + wps - 1) / wps;
+    u32x4 *my_tile = tile[wave];
+    u32x4 buf[P];
+    auto issue = [&](int step) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int q = i * kWave + lane;         // piece of the step, channel-major
+        const int ch = q / CH_PIECES, r = q % CH_PIECES;
+        const unsigned off = (unsigned)((ch * a.T + step * CH_SAMPLES) * SB + r * 16);
+        buf[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
+      }
+    };
+    const int my_piece = f * CH_PIECES + (j * S + s) * P;
+    issue(0);
+    for (int step = 0; step < n_steps; ++step) {
+      wave_lds_order();
+#pragma unroll
+      for (int i = 0; i < P; ++i) my_tile[i * kWave + lane] = buf[i];
+      wave_lds_order();
+      if (step + 1 < n_steps) issue(step + 1);
+      float ws[8] = {}, wr[8] = {};
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        float x[8];
+        if constexpr (FMT == FMT_CF32) {
+          const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k]);
+          const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k + 1]);
+          x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
+          x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
+        } else {
+          const f16x8 h = __builtin_bit_cast(f16x8, my_tile[my_piece + k]);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) x[e] = (float)h[e];
+        }
+        if constexpr (MIXED)
+          accumulate_sample_mixed(ws, wr, x, a.eps);
+        else
+          accumulate_sample(ws, wr, x, a.eps);
+      }
+      float tot[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) tot[e] = (MIXED && e >= 2) ? group_sum16_rt(ws[e], L) : group_sum_rt(ws[e], L);
+      const int w = step * wps + j;
+      const bool valid = w < a.nW;
+      // one lane per window plays the leader of finish_window; every lane folds
+      // its own raw partial into its own channel's sum
+      StreamAcc<1> one{};
+      const float wr1[1][8] = {{wr[0], wr[1], wr[2], wr[3], wr[4], wr[5], wr[6], wr[7]}};
+      if constexpr (MIXED) {
+        Thresholds t16{round16(th.s_low), round16(th.s_high), round16(th.g_re), round16(th.g_im)};
+        finish_window<1, true>(a, t16, tot, wr1, group * a.nW + w, valid, lane % L == 0, one);
+      } else {
+        finish_window<1>(a, th, tot, wr1, group * a.nW + w, valid, lane % L == 0, one);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[e] += one.sum[0][e];
+      kept += one.kept;
+      if (a.state != nullptr && one.mom.n > 0.0f) mom = moments_merge(mom, one.mom);
+    }
+  }
+  // masked sums: reduce over the lanes of each channel (skip the f bits of the lane index)
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    float v = acc[e];
+    for (int m = 1; m < kWave; m <<= 1)
+      if (m < S || m >= L) v += __shfl_xor(v, m);
+    acc[e] = v;
+  }
+  kept = group_sum<64>(kept);
+  if (a.state != nullptr) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) mom = moments_merge(mom, moments_shfl_xor(mom, m));
+  }
+  if (!active) return;
+  if (lane < L && s == 0) {                     // lane f S of window 0 writes channel f
+    const int64_t stream = group * F + f;
+    const float inv = kept > 0.0f ? 1.0f / kept : 0.0f;
+    f32x4 *out = reinterpret_cast<f32x4 *>(a.avg + stream * 8);
+    out[0] = f32x4{acc[0] * inv, acc[1] * inv, acc[2] * inv, acc[3] * inv};
+    out[1] = f32x4{acc[4] * inv, acc[5] * inv, acc[6] * inv, acc[7] * inv};
+    a.weight[stream] = kept * a.invT;
+  }
+  if (lane == 0 && a.state != nullptr && mom.n > 0.0f) {
+    StateRec *st = reinterpret_cast<StateRec *>(a.state) + group;
+    StateRec r = *st;
+    Moments old;
+    old.n = (float)r.n;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      old.m[k] = r.mean[k];
+      old.s[k] = r.m2[k];
+    }
+    const Moments nw = moments_merge(old, mom);
+    r.n += (uint32_t)mom.n;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      r.mean[k] = nw.m[k];
+      r.m2[k] = nw.s[k];
+    }
+    *st = r;
+  }
+}
+
 // Any window length (M >= 2, including M that is not a power of two) and
 // time x frequency windows of F = 1, 2 or 4 adjacent channels: one wave per
 // channel group, one lane per window, samples read directly.  Slower than the
@@ -467,6 +679,33 @@ hipError_t launch_generic(const ScreenArgs &a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+template <int FMT, int K, bool MIXED>
+hipError_t launch_windows_k(const ScreenArgs &a, hipStream_t stream) {
+  const int64_t blocks = (a.n_groups + kWavesPerBlock - 1) / kWavesPerBlock;
+  const dim3 grid((unsigned)blocks), block(kBlock);
+  switch (a.F) {
+    case 1: hipLaunchKernelGGL((screen_windows<FMT, K, 1, MIXED>), grid, block, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((screen_windows<FMT, K, 2, MIXED>), grid, block, 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((screen_windows<FMT, K, 4, MIXED>), grid, block, 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int FMT, bool MIXED>
+hipError_t launch_windows(int K, const ScreenArgs &a, hipStream_t stream) {
+  switch (K) {
+    case 2: return launch_windows_k<FMT, 2, MIXED>(a, stream);
+    case 3: return launch_windows_k<FMT, 3, MIXED>(a, stream);
+    case 4: return launch_windows_k<FMT, 4, MIXED>(a, stream);
+    case 5: return launch_windows_k<FMT, 5, MIXED>(a, stream);
+    case 6: return launch_windows_k<FMT, 6, MIXED>(a, stream);
+    case 7: return launch_windows_k<FMT, 7, MIXED>(a, stream);
+    case 8: return launch_windows_k<FMT, 8, MIXED>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 int ilog2_exact(int m) {
   int l = 0;
   while ((1 << l) < m) ++l;
@@ -509,12 +748,27 @@ bool tiled_supports(int M) {
   return l >= 1 && l <= kMaxTiledLog2M;
 }
 
+int windows_samples_per_lane(int M, int F) {
+  // largest power of two S dividing M with K = M / S <= 8, and F S <= 64 lanes per window
+  int S = 1;
+  while (M % (2 * S) == 0 && M / S > 8) S *= 2;
+  const int K = M / S;
+  if (K < 2 || K > 8 || F * S > kWave) return 0;
+  return K;
+}
+
 hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream) {
+  if (a.options & kOptPaperMixed) {  // complex64 storage and a windowed shape (checked by the plan)
+    const int K = windows_samples_per_lane(a.M, a.F);
+    return fmt == FMT_CF32 && K > 0 ? launch_windows<FMT_CF32, true>(K, a, stream) : hipErrorInvalidValue;
+  }
   const int l = ilog2_exact(a.M);
-  const bool tiled = a.F == 1 && l >= 1 && l <= kMaxTiledLog2M;
-  if (fmt == FMT_CF32) return tiled ? dispatch_tiled<FMT_CF32>(l, a, stream) : launch_generic<FMT_CF32>(a, stream);
-  if (fmt == FMT_CF16) return tiled ? dispatch_tiled<FMT_CF16>(l, a, stream) : launch_generic<FMT_CF16>(a, stream);
-  return hipErrorInvalidValue;
+  if (a.F == 1 && l >= 1 && l <= kMaxTiledLog2M)
+    return fmt == FMT_CF32 ? dispatch_tiled<FMT_CF32>(l, a, stream) : dispatch_tiled<FMT_CF16>(l, a, stream);
+  const int K = windows_samples_per_lane(a.M, a.F);
+  if (K > 0)
+    return fmt == FMT_CF32 ? launch_windows<FMT_CF32, false>(K, a, stream) : launch_windows<FMT_CF16, false>(K, a, stream);
+  return fmt == FMT_CF32 ? launch_generic<FMT_CF32>(a, stream) : launch_generic<FMT_CF16>(a, stream);
 }
 
 size_t probe_sink_floats() { return (size_t)kProbeBlocks * kWavesPerBlock; }

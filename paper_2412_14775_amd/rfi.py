@@ -30,6 +30,7 @@ RFI_VIS_CF16 = 1
 RFI_OPT_NO_SK = 1
 RFI_OPT_NO_DS = 2
 RFI_OPT_ADAPTIVE = 4
+RFI_OPT_PAPER_MIXED = 8
 
 RFI_FLAG_SK_LOW = 1
 RFI_FLAG_SK_HIGH = 2

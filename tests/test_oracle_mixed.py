@@ -1,0 +1,73 @@
+"""Pins of the paper's mixed-precision emulation (Tables 3-4) against binary16 error bounds
+of the float64 oracle (CPU only).  Parity of this form is pinned by error bounds only."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Params
+
+U16 = 2.0 ** -11                                 # unit roundoff of binary16
+
+
+def _cn(rng, shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * math.sqrt(0.5)
+
+
+def tau_bound(ref_tau, W, d):
+    """Group 7 is five binary16 roundings of O(1) quantities plus two input conversions:
+    |tau16 - tau64| <= 12 u max(1, pre * ratio) (a loose first-order bound)."""
+    pre = (W * d + 1) / (W - 1)
+    ratio = ref_tau / pre + 1
+    return 12 * U16 * np.maximum(1.0, pre * np.abs(ratio))
+
+
+def r_bound(W):
+    """Sequential binary16 sums of W unit-vector components: |partial_i| <= i, so the sum
+    errs by at most u (W(W+1)/2 + W); r = |sum| / W adds a few roundings."""
+    return math.sqrt(3) * U16 * (W * (W + 1) / 2 + W) / W + 6 * U16
+
+
+@pytest.mark.parametrize("W", [10, 20, 64])
+def test_mixed_statistics_within_binary16_bounds_of_float64(W):
+    rng = np.random.default_rng(80 + W)
+    win = (_cn(rng, (4000, W, 4)) * np.exp(rng.normal(0, 0.5, (4000, 1, 1)))).astype(np.complex64)
+    d = 1.7
+    t16, re16, im16 = oracle.mixed_window_stats(win, d, 2.0 ** -23)
+    I, Q, U, V = oracle.stokes(win.astype(np.complex128))
+    t64 = oracle.sk_tau(I, float(np.float32(d)), 2.0 ** -23)
+    re64 = oracle.ds_r(Q.real, U.real, V.real, 2.0 ** -23)
+    im64 = oracle.ds_r(Q.imag, U.imag, V.imag, 2.0 ** -23)
+    y = I.real ** 2 + I.imag ** 2
+    fits = W * y.sum(-1) < 65504 * (1 - 4 * U16)             # W S2 representable in binary16
+    assert np.isfinite(t16[fits]).all()
+    assert not np.isfinite(t16[W * y.sum(-1) > 65520]).any()   # overflow -> inf / NaN tau
+    ok = fits
+    assert np.all(np.abs(t16[ok].astype(float) - t64[ok]) <= tau_bound(t64[ok], W, d))
+    assert np.all(np.abs(re16.astype(float) - re64) <= r_bound(W))
+    assert np.all(np.abs(im16.astype(float) - im64) <= r_bound(W))
+    assert t16.dtype == np.float16 and re16.dtype == np.float16
+    # the emulation is not the float64 result: binary16 rounding is visible
+    assert np.abs(t16[ok].astype(float) - t64[ok]).max() > 1e-5
+
+
+def test_binary16_overflow_of_s2_flags_the_window():
+    """|I| of 300 in a 20-sample window: W S2 = 20 * 20 * 9e4 exceeds the binary16 range, the
+    ratio is inf / inf = NaN, and the negated low test flags the window (the overflow the
+    paper's reward penalises)."""
+    win = np.zeros((1, 1, 20, 4), np.complex64)
+    win[..., 0] = 300.0
+    out = oracle.screen_mixed(win, Params(M=20, s_low=0.1, s_high=5.0, gamma=1.0))
+    assert np.isnan(out["tau"][0, 0, 0]) or np.isinf(out["tau"][0, 0, 0])
+    assert out["flags"][0, 0, 0] & oracle.SK_LOW
+
+
+def test_mixed_flags_agree_with_float64_on_null_data():
+    """The paper reports under 1 % flag difference between 32-bit and the trained mixed form."""
+    rng = np.random.default_rng(90)
+    vis = _cn(rng, (6, 8, 2000, 4)).astype(np.complex64)
+    p = Params(M=10, F=2, d=1.0, s_low=0.45, s_high=2.0, gamma=0.43)
+    a = oracle.screen(vis, p)
+    b = oracle.screen_mixed(vis, p)
+    assert (a["flags"] != b["flags"]).mean() < 0.01
