@@ -211,6 +211,38 @@ def tf_window_form(steps: int, warmup: int):
     return res
 
 
+def mixed_case_form(steps: int, warmup: int):
+    """Larger mixed-RFI case: 64 stations (2080 baselines), 256 channels, 3072 samples, complex
+    half (26.2 GB per integration), M = 16, 64, 256."""
+    import torch
+    from paper_2412_14775_amd import rfi
+    dev = torch.device("cuda:0")
+    sc = synth.scene_mixed(3)
+    e = synth.device_voltages(sc, dev)
+    B, C, T = sc.n_baselines, sc.n_channels, sc.n_samples
+    vis = torch.empty((B, C, T, 4, 2), dtype=torch.float16, device=dev)
+    synth.correlate_torch(e, vis, "cf16")
+    del e
+    stream = torch.cuda.Stream(device=dev)
+    res = {"stations": sc.n_stations, "channels": C, "samples": T, "GB": B * C * T * 16 / 1e9}
+    for M in (16, 64, 256):
+        params = rfi.rfi_params_default(n_stations=sc.n_stations, n_baselines=B, n_channels=C, n_samples=T,
+                                        block_m=M, vis_format=rfi.RFI_VIS_CF16, sk_d=2.2, sk_low=0.5,
+                                        sk_high=1.6, ds_gamma=float(np.sqrt(7.815 / (3 * M))))
+        plan = rfi.Plan(params)
+        outs = plan.alloc_outputs(flags=True, stats=False)
+        with torch.cuda.stream(stream):
+            per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup)
+        plan.close()
+        alg = algorithmic_bytes(B * C, T, M, 16)
+        res[f"M{M}"] = {"samples_per_s": B * C * T * steps / (total_ms * 1e-3), "kernel_ms_mean": float(per.mean()),
+                        "achieved_GBs": alg / (per.mean() * 1e-3) / 1e9,
+                        "hbm_frac": alg / (per.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del vis
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving(seconds: float, rate: float):
     """Serving form: 16 arrays (12-64 stations, 16-256 channels, M = 64, complex half,
     adaptive thresholds), inputs pre-staged in HBM; Poisson arrivals at `rate` per second in
@@ -348,6 +380,7 @@ def main(argv=None):
     del vis32, vis16
     torch.cuda.empty_cache()
     tf = tf_window_form(max(10, args.steps // 4), max(2, args.warmup // 4))
+    mixed = mixed_case_form(max(10, args.steps // 4), max(2, args.warmup // 4))
     serve = serving(args.serving_seconds, 16.0) if args.serving_seconds > 0 else None
 
     f32 = forms["cf32"]
@@ -381,6 +414,7 @@ def main(argv=None):
         "cf16_over_cf32": forms["cf16"]["samples_per_s"] / f32["samples_per_s"],
         "read_probe_GBs": probe,
         "tf_window": tf,
+        "mixed_case_cf16": mixed,
         "serving": serve,
         "flagged_frac": f32["flagged_frac"],
         "kernel_source_digest": digest,

@@ -500,8 +500,11 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
       for (int i = 0; i < P; ++i) {
         const int q = i * kWave + lane;         // piece of the step, channel-major
         const int ch = q / CH_PIECES, r = q % CH_PIECES;
+        // pieces past the end of the channel (ragged last step) belong to no valid window
+        const bool inside = step * CH_SAMPLES + r / PPS < a.T;
         const unsigned off = (unsigned)((ch * a.T + step * CH_SAMPLES) * SB + r * 16);
-        buf[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
+        buf[i] = inside ? __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming))
+                        : u32x4{0u, 0u, 0u, 0u};
       }
     };
     const int my_piece = f * CH_PIECES + (j * S + s) * P;
@@ -715,23 +718,34 @@ int ilog2_exact(int m) {
 // ----------------------------------------------------------------------------- probes
 
 constexpr int kProbeBlocks = 4096;
+constexpr int kProbeChunk = 16384;  // bytes per wave per step
 
+// Read-only probe with the screen's access pattern at its best: each wave streams
+// contiguous 16 KiB steps of its own chunk with coalesced non-temporal 16-byte
+// loads; the chunks of consecutive waves are adjacent.
 __global__ void __launch_bounds__(kBlock) probe_read_kernel(const u32x4 *src, size_t n16, float *sink) {
-  const size_t stride = (size_t)gridDim.x * kBlock;
+  const int lane = threadIdx.x % kWave;
+  const size_t waves = (size_t)gridDim.x * kWavesPerBlock;
+  const size_t wave = (size_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  const size_t n_steps = (n16 * 16 + kProbeChunk - 1) / kProbeChunk;
+  const uint8_t *base = reinterpret_cast<const uint8_t *>(src);
+  const size_t total = n16 * 16;
   u32x4 acc = {0u, 0u, 0u, 0u};
-  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  for (; i + 3 * stride < n16; i += 4 * stride) {
-    const u32x4 v0 = __builtin_nontemporal_load(src + i);
-    const u32x4 v1 = __builtin_nontemporal_load(src + i + stride);
-    const u32x4 v2 = __builtin_nontemporal_load(src + i + 2 * stride);
-    const u32x4 v3 = __builtin_nontemporal_load(src + i + 3 * stride);
-    acc ^= v0 ^ v1 ^ v2 ^ v3;
+  for (size_t step = wave; step < n_steps; step += waves) {
+    const size_t off = step * kProbeChunk;
+    const size_t len = total - off < (size_t)kProbeChunk ? total - off : (size_t)kProbeChunk;
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(base + off), (short)0, (int)len, kRsrcWord3);
+    u32x4 v[kProbeChunk / 1024];
+#pragma unroll
+    for (int i = 0; i < kProbeChunk / 1024; ++i)
+      v[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (i * kWave + lane) * 16, 0, kLoadStreaming));
+#pragma unroll
+    for (int i = 0; i < kProbeChunk / 1024; ++i) acc ^= v[i];
   }
-  for (; i < n16; i += stride) acc ^= __builtin_nontemporal_load(src + i);
   unsigned x = acc[0] ^ acc[1] ^ acc[2] ^ acc[3];
   for (int m = 1; m < kWave; m <<= 1) x ^= __shfl_xor(x, m);
-  if ((threadIdx.x % kWave) == 0)
-    sink[(size_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave] = __builtin_bit_cast(float, x);
+  if (lane == 0) sink[wave] = __builtin_bit_cast(float, x);
 }
 
 __global__ void __launch_bounds__(kBlock) probe_copy_kernel(u32x4 *dst, const u32x4 *src, size_t n16) {
