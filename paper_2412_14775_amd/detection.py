@@ -15,9 +15,12 @@ from __future__ import annotations
 import numpy as np
 
 
-def _scene(synth, seed, N, C, T, inr_db, polarized, rng):
+def _scene(synth, seed, N, C, T, inr_db, polarized, rng, model="voltage"):
     """Narrow-duration and narrowband sources at random places; pol_frac U[0.5, 0.9] when
-    polarised (at most 90 % polarised, as at the horizon), fully unpolarised otherwise."""
+    polarised (at most 90 % polarised, as at the horizon), fully unpolarised otherwise.
+    model "voltage": injected into the station voltages (per-sample polarisation wanders
+    around the mean state); model "post": added after correlation with a fixed coherency of
+    that degree of polarisation (the simulation model of Section 4.2)."""
     srcs = []
     for _ in range(3):                                     # narrow duration, 1-2 channels
         start = int(rng.integers(0, T - 60))
@@ -33,6 +36,10 @@ def _scene(synth, seed, N, C, T, inr_db, polarized, rng):
                           synth.pulse_train(T, int(rng.integers(100, 400)), int(rng.integers(10, 40)), 0),
                           f0=float(rng.uniform(-0.5, 0.5)), unpolarized=not polarized,
                           pol_frac=float(rng.uniform(0.5, 0.9)) if polarized else 1.0))
+    if model == "post":
+        post = [synth.PostRfi(s.channels, s.inr_db, s.theta, s.chi, s.envelope,
+                              0.0 if s.unpolarized else s.pol_frac) for s in srcs]
+        return synth.Scene(N, C, T, seed, rho=0.1, post_rfi=post)
     return synth.Scene(N, C, T, seed, rho=0.1, rfi=srcs)
 
 
@@ -43,7 +50,7 @@ def _window_truth(truth, M, F):
 
 
 def detection_study(inrs_db=(-10, -5, 0, 5, 10, 20), realizations=4, N=6, C=16, T=2000, M=10, F=2,
-                    fmt="cf32", pfa_sk=0.01, pfa_ds=0.01, seed=0):
+                    fmt="cf32", pfa_sk=0.01, pfa_ds=0.01, seed=0, model="voltage"):
     """Pfa / Pmd table for SK, DS and BOTH, polarised and unpolarised RFI."""
     import torch
 
@@ -72,8 +79,8 @@ def detection_study(inrs_db=(-10, -5, 0, 5, 10, 20), realizations=4, N=6, C=16, 
             counts = {m: np.zeros(4, np.int64) for m in methods}     # fa, clean, md, rfi
             for k in range(realizations):
                 sc = _scene(synth, seed * 100_000 + 1000 * ii + 17 * k + (0 if polarized else 500), N, C, T,
-                            float(inr), polarized, rng)
-                vis = to_dev(synth.correlate(synth.make_voltages(sc)))
+                            float(inr), polarized, rng, model)
+                vis = to_dev(synth.correlate_scene(sc, synth.make_voltages(sc)))
                 truth = _window_truth(synth.rfi_truth(sc), M, F)      # same for every baseline
                 for name, opt in methods.items():
                     p = rfi.rfi_params_default(**{**base.as_dict(), **cal, "options": opt})
@@ -89,7 +96,7 @@ def detection_study(inrs_db=(-10, -5, 0, 5, 10, 20), realizations=4, N=6, C=16, 
                 rows.append(dict(polarized=polarized, inr_db=float(inr), method=name,
                                  pfa=float(c[0] / max(c[1], 1)), pmd=float(c[2] / max(c[3], 1)),
                                  rfi_windows=int(c[3])))
-    return dict(calibration=cal, window=f"{M} x {F}", stations=N, channels=C, samples=T, rows=rows)
+    return dict(calibration=cal, window=f"{M} x {F}", stations=N, channels=C, samples=T, model=model, rows=rows)
 
 
 def format_table(study) -> str:

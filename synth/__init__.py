@@ -36,7 +36,8 @@ __all__ = [
     "baseline_pairs", "n_baselines", "jones", "inr_to_amplitude", "Rfi",
     "Scene", "make_voltages", "correlate", "correlate_torch", "to_cf16",
     "scene_plain", "scene_fp32_baseline", "scene_mixed", "scene_null",
-    "scene_serving_array", "rfi_truth", "device_voltages", "serving_mix",
+    "scene_serving_array", "rfi_truth", "device_voltages", "serving_mix", "PostRfi",
+    "correlate_scene",
 ]
 
 
@@ -65,6 +66,19 @@ def jones(theta: float, chi: float) -> np.ndarray:
 def inr_to_amplitude(inr_db: float) -> float:
     """Voltage amplitude A for an in-pulse INR (dB): INR = A^2 / 2 for unit-variance noise per pol."""
     return float(np.sqrt(2.0 * 10.0 ** (inr_db / 10.0)))
+
+
+@dataclass
+class PostRfi:
+    """RFI added after correlation with a fixed coherency (the simulation model of Section 4.2):
+    V_pq += A^2 g(t) exp(i (phi_p - phi_q)) C,  C = pol_frac j j^H + (1 - pol_frac) I / 2,
+    so its degree of polarisation is pol_frac and tr C = 1 (INR = A^2 / 2 as for Rfi)."""
+    channels: Sequence[int]
+    inr_db: float
+    theta: float = 0.0
+    chi: float = 0.0
+    envelope: Optional[np.ndarray] = None
+    pol_frac: float = 1.0
 
 
 @dataclass
@@ -116,6 +130,7 @@ class Scene:
     rfi: List[Rfi] = field(default_factory=list)
     noise_scale: float = 1.0
     noise_free: bool = False       # RFI only (for closed-form checks)
+    post_rfi: List[PostRfi] = field(default_factory=list)
 
     @property
     def n_baselines(self) -> int:
@@ -174,7 +189,7 @@ def make_voltages(scene: Scene) -> np.ndarray:
 def rfi_truth(scene: Scene) -> np.ndarray:
     """Boolean [C][T]: True where any RFI source is on (ground truth for detection studies)."""
     truth = np.zeros((scene.n_channels, scene.n_samples), bool)
-    for src in scene.rfi:
+    for src in list(scene.rfi) + list(scene.post_rfi):
         g = np.ones(scene.n_samples, bool) if src.envelope is None else src.envelope > 0
         for c in src.channels:
             truth[c] |= g
@@ -208,6 +223,27 @@ def _hermitian_autos(out, is_auto):
     a[..., 3] = a[..., 3].real
     a[..., 2] = np.conj(a[..., 1])
     out[is_auto] = a
+
+
+def correlate_scene(scene: Scene, e: np.ndarray) -> np.ndarray:
+    """Visibilities of a scene: voltage products, then its post-correlation RFI sources."""
+    vis = correlate(e)
+    if not scene.post_rfi:
+        return vis
+    rng = np.random.default_rng(scene.seed + 7_000_003)
+    p, q = baseline_pairs(scene.n_stations)
+    for src in scene.post_rfi:
+        A2 = inr_to_amplitude(src.inr_db) ** 2
+        j = jones(src.theta, src.chi)
+        coh = src.pol_frac * np.outer(j, j.conj()) + (1.0 - src.pol_frac) * 0.5 * np.eye(2)
+        coh = np.array([[coh[0, 0].real, coh[0, 1]], [np.conj(coh[0, 1]), coh[1, 1].real]])  # exactly Hermitian
+        phi = rng.uniform(0.0, 2 * np.pi, size=scene.n_stations)
+        g = np.ones(scene.n_samples) if src.envelope is None else src.envelope
+        ph = np.exp(1j * (phi[p] - phi[q]))                                  # [B]
+        add = (A2 * ph[:, None, None] * g[None, :, None] * coh.reshape(4)[None, None, :])
+        for c in src.channels:
+            vis[:, c] += add.astype(np.complex64)
+    return vis
 
 
 def correlate_torch(e_dev, out_dev, fmt: str = "cf32", chunk: int = 64):

@@ -22,3 +22,20 @@ def test_energy_and_polarisation_statistics_complement_each_other():
             both = r[pol, inr, "BOTH"]["pmd"]
             assert both <= min(r[pol, inr, "SK"]["pmd"], r[pol, inr, "DS"]["pmd"]) + 1e-12
         assert r[pol, 20.0, "BOTH"]["pmd"] < r[pol, -5.0, "BOTH"]["pmd"]
+
+
+def test_post_correlation_rfi_model():
+    """RFI added after correlation with a fixed coherency (the paper's simulation): polarised
+    RFI is caught by the directional statistic at least as well as by SK from 10 dB on, and
+    unpolarised RFI only by SK."""
+    from paper_2412_14775_amd.detection import detection_study, format_table
+    study = detection_study(inrs_db=(-5, 0, 10, 20), realizations=3, model="post")
+    print("\n" + format_table(study))
+    r = {(x["polarized"], x["inr_db"], x["method"]): x for x in study["rows"]}
+    assert r[False, 20.0, "DS"]["pmd"] > 0.5
+    assert r[False, 20.0, "SK"]["pmd"] < r[False, 20.0, "DS"]["pmd"]
+    for pol in (True, False):
+        for inr in (-5.0, 0.0, 10.0, 20.0):
+            assert r[pol, inr, "BOTH"]["pmd"] <= min(r[pol, inr, "SK"]["pmd"], r[pol, inr, "DS"]["pmd"]) + 1e-12
+    for x in study["rows"]:
+        assert x["pfa"] < 0.06
