@@ -38,7 +38,6 @@ N_STATIONS, N_CHANNELS, N_SAMPLES, BLOCK_M = 48, 64, 3072, 64
 SEED = 1
 # plan thresholds for M = 64 (null quantiles of this generator: SK 2.5 / 97.5 %, DS 95 %)
 PLAN = dict(sk_d=2.2, sk_low=0.656, sk_high=1.487, ds_gamma=0.202)
-SCREEN_KERNEL = "screen_tiled"
 CPU_SAMPLE_BASELINES = 300          # baselines (x all 64 channels) screened by the oracle
 
 
@@ -156,7 +155,7 @@ def copy_calibration(buf, stream, reps=3):
     torch.cuda.synchronize()
 
 
-def stored_traffic(digest: str, per_launch_alg: float):
+def stored_traffic(digest: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
     this exact kernel source; None otherwise."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -385,7 +384,7 @@ def main(argv=None):
 
     f32 = forms["cf32"]
     digest = kernel_source_digest()
-    traffic = stored_traffic(digest, f32["bytes_per_launch"])
+    traffic = stored_traffic(digest)
     line = {
         "metric": "visibility samples/s screened (FP16 vs FP32, % HBM peak); p99 latency/integ",
         "value": f32["samples_per_s"],

@@ -54,8 +54,6 @@ constexpr int kMaxTiledLog2M = 12;  // tiled kernels exist for M = 2 .. 4096
 
 // Kernel selection.  Returns hipErrorInvalidValue when no kernel matches.
 hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream);
-// Samples per lane per iteration of the tiled kernel for a format (4 for CF32, 8 for CF16).
-int tiled_samples_per_lane(int fmt);
 bool tiled_supports(int M);
 // Samples per lane of the windowed kernel for (M, F), or 0 when it does not apply.
 int windows_samples_per_lane(int M, int F);

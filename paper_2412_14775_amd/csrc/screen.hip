@@ -1,7 +1,14 @@
 // screen.hip -- gfx950 kernels of the online energy + polarisation RFI screen
 // (arXiv 2412.14775, Section 2, Tables 1-2).
 //
-// One pass over the visibilities, bound by HBM bandwidth:
+// Three kernels share the per-sample and per-window code below:
+//   screen_tiled    time-only windows of M = 2^k samples (the hot path);
+//   screen_windows  windows of M = K S samples x F channels (non-power-of-two M and
+//                   the paper's time x frequency windows), optionally in the
+//                   paper's mixed precision (Tables 3-4);
+//   screen_generic  any other shape, one lane per window.
+//
+// screen_tiled, one pass over the visibilities, bound by HBM bandwidth:
 //   * each wave owns one stream (baseline, channel) or a window-aligned segment
 //     of it, and walks it in 8 KiB steps;
 //   * a step is read with fully coalesced 16-byte buffer loads (lane l takes
@@ -754,8 +761,6 @@ __global__ void __launch_bounds__(kBlock) probe_copy_kernel(u32x4 *dst, const u3
 }
 
 }  // namespace
-
-int tiled_samples_per_lane(int fmt) { return fmt == FMT_CF32 ? 4 : 8; }
 
 bool tiled_supports(int M) {
   const int l = ilog2_exact(M);
