@@ -70,6 +70,17 @@ def test_plain_case_cf32():
     assert 0.05 < rep["flagged_frac"] < 0.6
 
 
+def test_plain_case_against_stored_oracle_outputs():
+    """GPU results against the committed oracle outputs (tests/golden/plain_case_oracle.npz)."""
+    from tests.golden.make_golden import OUT, PARAMS
+    g = np.load(OUT)
+    vis = synth.correlate(synth.make_voltages(synth.scene_plain(0)))
+    kw = {k: v for k, v in PARAMS.items() if k != "M"}
+    op, gpu = screen_both(vis, PARAMS["M"], **kw)
+    ref = {k: g[k] for k in ("tau", "r_re", "r_im", "flags", "avg", "weight")}
+    compare(gpu, vis, op, TOL_F32, ref=ref, label="stored plain case")
+
+
 def test_plain_case_cf16():
     vis = synth.correlate(synth.make_voltages(synth.scene_plain(0)))
     rep_a, rep_t = check_cf16(vis, 16, "plain cf16", **thresholds_for(16))
