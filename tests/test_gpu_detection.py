@@ -26,13 +26,14 @@ def test_energy_and_polarisation_statistics_complement_each_other():
 
 def test_post_correlation_rfi_model():
     """RFI added after correlation with a fixed coherency (the paper's simulation): polarised
-    RFI is caught by the directional statistic at least as well as by SK from 10 dB on, and
-    unpolarised RFI only by SK."""
+    RFI is caught by the directional statistic better than by SK, unpolarised RFI only by SK."""
     from paper_2412_14775_amd.detection import detection_study, format_table
     study = detection_study(inrs_db=(-5, 0, 10, 20), realizations=3, model="post")
     print("\n" + format_table(study))
     r = {(x["polarized"], x["inr_db"], x["method"]): x for x in study["rows"]}
-    assert r[False, 20.0, "DS"]["pmd"] > 0.5
+    for inr in (0.0, 10.0, 20.0):      # polarised RFI: DS misses less than SK (Fig. 3a)
+        assert r[True, inr, "DS"]["pmd"] < r[True, inr, "SK"]["pmd"]
+    assert r[False, 20.0, "DS"]["pmd"] > 0.5     # unpolarised RFI: DS is blind (Fig. 3b)
     assert r[False, 20.0, "SK"]["pmd"] < r[False, 20.0, "DS"]["pmd"]
     for pol in (True, False):
         for inr in (-5.0, 0.0, 10.0, 20.0):
