@@ -649,11 +649,18 @@ __global__ void __launch_bounds__(kBlock) screen_generic(const ScreenArgs a) {
   finish_stream<F>(a, acc, group, 0, active, wave, lane, xfer);
 }
 
+// Unused dynamic LDS that caps the complex64 tiled kernel at three blocks (12 waves) per CU
+// (33 KiB static + 7.5 KiB > 160 KiB / 4).  Its registers alone would allow 16 waves; with fewer
+// streams read at once the kernel streams 1-2 % faster.  The complex-half kernel is held at
+// 12 waves by its registers already.
+constexpr unsigned kCf32OccupancyPad = 7680;
+
 template <int FMT, int LOG2M>
 hipError_t launch_tiled(const ScreenArgs &a, hipStream_t stream) {
   const int64_t units = a.n_groups * a.n_seg;
   const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL((screen_tiled<FMT, LOG2M>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, a);
+  const unsigned pad = FMT == FMT_CF32 ? kCf32OccupancyPad : 0u;
+  hipLaunchKernelGGL((screen_tiled<FMT, LOG2M>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
   return hipGetLastError();
 }
 
