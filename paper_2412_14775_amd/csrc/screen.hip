@@ -605,10 +605,24 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
   }
 }
 
+// s += b with the running compensation c (Kahan): the error of a long sum of
+// block sums stays at a few ulps whatever the number of blocks.
+__device__ __forceinline__ void compensated_add(float &s, float &c, float b) {
+  const float y = b - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+constexpr int kGenericBlock = 64;  // samples summed plainly before a compensated add
+
 // Any window length (M >= 2, including M that is not a power of two) and
 // time x frequency windows of F = 1, 2 or 4 adjacent channels: one wave per
 // channel group, one lane per window, samples read directly.  Slower than the
-// tiled kernel; used for the shapes the tiled kernel does not cover.
+// tiled kernel; used for the shapes the tiled kernel does not cover.  A lane
+// sums its window alone, so the sums run in blocks of 64 samples (as long as
+// the sequential runs of the other kernels) folded in with compensation: the
+// rounding error does not grow with M.
 template <int FMT, int F>
 __global__ void __launch_bounds__(kBlock) screen_generic(const ScreenArgs a) {
   constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
@@ -624,23 +638,33 @@ __global__ void __launch_bounds__(kBlock) screen_generic(const ScreenArgs a) {
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t *>(base), (short)0, F * a.T * SB, kRsrcWord3);
     for (int w = lane; w < a.nW; w += kWave) {
-      float ws[8] = {}, wr[F][8] = {};
+      float ws[8] = {}, wr[F][8] = {}, cs[8] = {};
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        for (int t = 0; t < a.M; ++t) {
-          const unsigned off = (unsigned)((f * a.T + w * a.M + t) * SB);
-          float x[8];
-          if constexpr (FMT == FMT_CF32) {
-            const f32x4 lo = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
-            const f32x4 hi = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + 16, 0, kLoadStreaming));
-            x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
-            x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
-          } else {
-            const f16x8 h = __builtin_bit_cast(f16x8, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
+        float cr[8] = {};
+        for (int t0 = 0; t0 < a.M; t0 += kGenericBlock) {
+          const int t1 = min(a.M, t0 + kGenericBlock);
+          float bs[8] = {}, br[8] = {};
+          for (int t = t0; t < t1; ++t) {
+            const unsigned off = (unsigned)((f * a.T + w * a.M + t) * SB);
+            float x[8];
+            if constexpr (FMT == FMT_CF32) {
+              const f32x4 lo = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
+              const f32x4 hi = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + 16, 0, kLoadStreaming));
+              x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
+              x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
+            } else {
+              const f16x8 h = __builtin_bit_cast(f16x8, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
 #pragma unroll
-            for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
+              for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
+            }
+            accumulate_sample(bs, br, x, a.eps);
           }
-          accumulate_sample(ws, wr[f], x, a.eps);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            compensated_add(ws[k], cs[k], bs[k]);
+            compensated_add(wr[f][k], cr[k], br[k]);
+          }
         }
       }
       finish_window<F>(a, th, ws, wr, group * a.nW + w, true, true, acc);
