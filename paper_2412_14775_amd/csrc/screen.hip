@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
       for (int i = 0; i < kPieces; ++i)
         buf[i] = __builtin_bit_cast(
             u32x4, __builtin_amdgcn_raw_buffer_load_b128(
-                       rsrc, (unsigned)(step * SPI * SB + (i * kWave + lane) * 16), 0, kLoadStreaming));
+                       rsrc, (unsigned)(step * SPI * SB) + (unsigned)((i * kWave + lane) * 16), 0, kLoadStreaming));
     };
 
     float ws[8] = {}, wr[1][8] = {};
@@ -509,7 +509,7 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
         const int ch = q / CH_PIECES, r = q % CH_PIECES;
         // pieces past the end of the channel (ragged last step) belong to no valid window
         const bool inside = step * CH_SAMPLES + r / PPS < a.T;
-        const unsigned off = (unsigned)((ch * a.T + step * CH_SAMPLES) * SB + r * 16);
+        const unsigned off = (unsigned)(ch * a.T + step * CH_SAMPLES) * SB + (unsigned)(r * 16);  // may pass 2^31 when !inside
         buf[i] = inside ? __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming))
                         : u32x4{0u, 0u, 0u, 0u};
       }
@@ -646,7 +646,7 @@ __global__ void __launch_bounds__(kBlock) screen_generic(const ScreenArgs a) {
           const int t1 = min(a.M, t0 + kGenericBlock);
           float bs[8] = {}, br[8] = {};
           for (int t = t0; t < t1; ++t) {
-            const unsigned off = (unsigned)((f * a.T + w * a.M + t) * SB);
+            const unsigned off = (unsigned)(f * a.T + w * a.M + t) * SB;
             float x[8];
             if constexpr (FMT == FMT_CF32) {
               const f32x4 lo = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
