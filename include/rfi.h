@@ -214,7 +214,11 @@ int rfi_calibrate_from_stats(const float *stats, size_t n_windows, int32_t W, fl
  * does not block later requests of other plans.  Each admitted request replays a hipGraph
  * of its screen step (captured on first use for that plan and buffer set) on its slot's
  * stream; a host callback timestamps completion.  Requests of different arrays therefore
- * overlap on the device, and each result is bitwise the same as when run alone.
+ * overlap on the device, and each result is bitwise the same as when run alone.  Graphs
+ * are cached per plan identity, not per plan address: a plan created after another was
+ * destroyed never replays the old plan's graph, even at the same address.  A failed
+ * request completes with its status in rfi_completion.status; its message is recorded on
+ * the scheduler thread, so rfi_last_error on the caller's thread does not show it.
  * ------------------------------------------------------------------------------------------ */
 typedef struct rfi_server rfi_server; /* opaque */
 

@@ -3,6 +3,7 @@
 // reporting.  Every argument check runs before any HIP call, so invalid input
 // is rejected without touching a device.
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -12,6 +13,7 @@
 
 #include "../../include/rfi.h"
 #include "internal.h"
+#include "plan.h"
 
 struct rfi_plan {
   rfi_params p;
@@ -23,11 +25,13 @@ struct rfi_plan {
   size_t sample_bytes;
   void *state;  // device, n_streams * 32 bytes, ADAPTIVE only
   size_t state_bytes;
+  uint64_t uid;  // rfi::plan_uid
 };
 
 namespace {
 
 thread_local std::string g_error;
+std::atomic<uint64_t> g_next_plan_uid{1};
 
 int fail(int code, const char *fmt, ...) {
   char buf[512];
@@ -124,6 +128,8 @@ int choose_segments(const rfi_params &p, int64_t n_streams) {
 
 }  // namespace
 
+uint64_t rfi::plan_uid(const rfi_plan *plan) { return plan->uid; }
+
 int rfi::set_error(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
@@ -165,6 +171,7 @@ int rfi_plan_create(const rfi_params *params, int device, rfi_plan **out) {
   rfi_plan *plan = new (std::nothrow) rfi_plan{};
   if (plan == nullptr) return fail(RFI_ERR_OUT_OF_MEMORY, "host allocation of the plan failed");
   plan->p = *params;
+  plan->uid = g_next_plan_uid.fetch_add(1);
   plan->device = device;
   plan->n_streams = (int64_t)params->n_baselines * params->n_channels;
   plan->n_groups = plan->n_streams / params->block_f;

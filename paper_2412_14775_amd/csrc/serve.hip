@@ -25,13 +25,17 @@
 
 #include "../../include/rfi.h"
 #include "internal.h"
+#include "plan.h"
 
 namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// A cached graph holds the plan's kernel arguments, so it is keyed by the plan's
+// uid (never reused) rather than its address (reused once a plan is destroyed).
 struct GraphKey {
-  const void *plan, *vis, *avg, *weight, *flags, *stats;
+  uint64_t plan;
+  const void *vis, *avg, *weight, *flags, *stats;
   bool operator<(const GraphKey &o) const {
     return std::tie(plan, vis, avg, weight, flags, stats) < std::tie(o.plan, o.vis, o.avg, o.weight, o.flags, o.stats);
   }
@@ -108,7 +112,7 @@ void rfi_server::on_done(void *p) {
 int rfi_server::launch(int slot, const rfi_request &r) {
   hipStream_t st = streams[slot];
   if (!cfg.use_graphs) return rfi_screen(r.plan, r.vis, r.avg, r.weight, r.flags, r.stats, st);
-  const GraphKey key{r.plan, r.vis, r.avg, r.weight, r.flags, r.stats};
+  const GraphKey key{rfi::plan_uid(r.plan), r.vis, r.avg, r.weight, r.flags, r.stats};
   auto it = graphs.find(key);
   if (it == graphs.end()) {
     hipGraph_t g = nullptr;

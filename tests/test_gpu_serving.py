@@ -137,6 +137,40 @@ def test_requests_overlap_in_flight():
     torch.cuda.empty_cache()
 
 
+def test_recreated_plan_gets_its_own_graph():
+    """A plan is served, destroyed, and another with different thresholds created (the allocator
+    usually hands it the same host address) and served into the same buffers: the server must not
+    replay the first plan's cached graph, whose kernel arguments hold the old thresholds."""
+    import torch
+    from paper_2412_14775_amd import rfi
+    N, C = 4, 8
+    B = N * (N + 1) // 2
+    vis = synth.to_cf16(synth.correlate(synth.make_voltages(synth.Scene(N, C, T, seed=11))))
+    dev = to_device(vis, "cf16")
+    srv = rfi.Server(n_slots=2)
+    out, served, addresses = None, [], []
+    for s_high in (1.6, 1.05):
+        _, rp = make_params(B, C, T, M, "cf16", d=2.2, s_low=0.5, s_high=s_high, gamma=0.3)
+        plan = rfi.Plan(rp)
+        addresses.append(int(plan.handle))
+        if out is None:
+            out = plan.alloc_outputs(flags=True, stats=False)
+        srv.submit(plan, dev, out, tag=len(served))
+        srv.drain(30)
+        assert srv.poll(10)[0]["status"] == 0
+        served.append(out["flags"].cpu().numpy().copy())
+        ref = plan.alloc_outputs(flags=True, stats=False)
+        plan.screen(dev, ref["avg"], ref["weight"], ref["flags"], None)
+        torch.cuda.synchronize()
+        assert np.array_equal(served[-1], ref["flags"].cpu().numpy()), f"served flags differ (s_high={s_high})"
+        plan.close()
+    st = srv.stats()
+    srv.close()
+    print("plan addresses", [hex(x) for x in addresses])
+    assert st["graphs"] == 2
+    assert not np.array_equal(served[0], served[1])
+
+
 def test_admission_respects_the_hbm_budget():
     import torch
     from paper_2412_14775_amd import rfi
