@@ -261,7 +261,10 @@ int rfi_server_create(const rfi_server_config *cfg, rfi_server **out);
 /* Seconds since the server was created (monotonic clock). */
 double rfi_server_now(const rfi_server *srv);
 /* Queue a request (thread-safe; returns at once).  INVALID_ARGUMENT if a pointer is NULL or
- * the plan's footprint alone exceeds the budget (the request could never be admitted). */
+ * the plan's footprint alone exceeds the budget (the request could never be admitted).
+ * The server's streams wait on no other stream: the input must be complete in device memory
+ * when the request is submitted (synchronize the stream that produced it first), and the
+ * buffers must stay untouched until the request's completion has been polled. */
 int rfi_server_submit(rfi_server *srv, const rfi_request *req);
 /* Move up to `max` completions into `out` (*n_out of them), waiting up to timeout_s seconds
  * for at least one.  Completions are returned in the order the device finished them. */

@@ -417,6 +417,8 @@ class Server:
         plan._check_tensor("stats", out.get("stats"), (plan.B, plan.G, plan.nW, 3), torch.float32)
         if tag in self._live:
             raise ValueError(f"tag {tag} is already in flight")
+        # the server's streams wait on no other stream: finish whatever produced the inputs
+        torch.cuda.current_stream(plan.device).synchronize()
         self._live[tag] = (vis, out)
         try:
             rfi_server_submit(self.handle, plan.handle, vis, out["avg"], out["weight"], out.get("flags"),
