@@ -26,6 +26,7 @@
 #include "../../include/rfi.h"
 #include "internal.h"
 #include "plan.h"
+#include "serve_policy.h"
 
 namespace {
 
@@ -147,16 +148,15 @@ void rfi_server::run() {
       future.erase(future.begin());
     }
     // admission: FIFO, skipping requests that cannot go yet; a plan stays in order
-    std::set<const rfi_plan *> blocked;
-    for (auto it = queue.begin(); it != queue.end();) {
-      const rfi_plan *plan = it->req.plan;
-      bool plan_busy = blocked.count(plan) > 0;
-      for (int s = 0; s < cfg.n_slots && !plan_busy; ++s) plan_busy = slot_busy[s] && slot_plan[s] == plan;
-      if (plan_busy || inflight_bytes + it->bytes > cfg.hbm_budget) {
-        blocked.insert(plan);
-        ++it;
-        continue;
-      }
+    // (rfi::first_admissible); one request per free slot
+    auto plan_of = [](const Pending &q) { return static_cast<const void *>(q.req.plan); };
+    auto bytes_of = [](const Pending &q) { return q.bytes; };
+    auto running = [this](const void *plan) {
+      for (int s = 0; s < cfg.n_slots; ++s)
+        if (slot_busy[s] && slot_plan[s] == plan) return true;
+      return false;
+    };
+    for (;;) {
       int slot = -1;
       for (int s = 0; s < cfg.n_slots; ++s)
         if (!slot_busy[s]) {
@@ -164,8 +164,11 @@ void rfi_server::run() {
           break;
         }
       if (slot < 0) break;
-      const Pending p = *it;
-      it = queue.erase(it);  // only this thread touches `queue`: `it` stays valid across the unlock
+      const std::ptrdiff_t k = rfi::first_admissible(queue, plan_of, bytes_of, running, inflight_bytes, cfg.hbm_budget);
+      if (k < 0) break;
+      const Pending p = queue[k];
+      const rfi_plan *plan = p.req.plan;
+      queue.erase(queue.begin() + k);  // only this thread touches `queue`
       slot_busy[slot] = true;
       slot_plan[slot] = plan;
       slot_bytes[slot] = p.bytes;
