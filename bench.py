@@ -210,6 +210,41 @@ def tf_window_form(steps: int, warmup: int):
     return res
 
 
+def long_window_form(steps: int, warmup: int):
+    """One window per integration (M = T = 3072, not a power of two times a small factor):
+    the long-window kernel on the 48-station, 64-channel array, complex64 and complex half."""
+    import torch
+    from paper_2412_14775_amd import rfi
+    dev = torch.device("cuda:0")
+    sc = synth.scene_fp32_baseline(SEED, N_STATIONS, N_CHANNELS, N_SAMPLES)
+    e = synth.device_voltages(sc, dev)
+    B, C, T = sc.n_baselines, sc.n_channels, sc.n_samples
+    vis32 = torch.empty((B, C, T, 4, 2), dtype=torch.float32, device=dev)
+    synth.correlate_torch(e, vis32, "cf32")
+    del e
+    stream = torch.cuda.Stream(device=dev)
+    res = {"window": f"{T} x 1", "samples": T}
+    for name, fmt, sb in (("cf32", rfi.RFI_VIS_CF32, 32), ("cf16", rfi.RFI_VIS_CF16, 16)):
+        vis = vis32 if fmt == rfi.RFI_VIS_CF32 else vis32.to(torch.float16)
+        params = rfi.rfi_params_default(n_stations=N_STATIONS, n_baselines=B, n_channels=C, n_samples=T,
+                                        block_m=T, vis_format=fmt, sk_d=2.2, sk_low=0.9, sk_high=1.1,
+                                        ds_gamma=0.03)
+        plan = rfi.Plan(params)
+        outs = plan.alloc_outputs(flags=True, stats=False)
+        with torch.cuda.stream(stream):
+            per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup)
+        plan.close()
+        alg = algorithmic_bytes(B * C, T, T, sb)
+        res[name] = {"samples_per_s": B * C * T * steps / (total_ms * 1e-3),
+                     "kernel_ms_mean": float(per.mean()),
+                     "achieved_GBs": alg / (per.mean() * 1e-3) / 1e9,
+                     "hbm_frac": alg / (per.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del vis
+    del vis32
+    torch.cuda.empty_cache()
+    return res
+
+
 def mixed_case_form(steps: int, warmup: int):
     """Larger mixed-RFI case: 64 stations (2080 baselines), 256 channels, 3072 samples, complex
     half (26.2 GB per integration), M = 16, 64, 256."""
@@ -379,6 +414,7 @@ def main(argv=None):
     del vis32, vis16
     torch.cuda.empty_cache()
     tf = tf_window_form(max(10, args.steps // 4), max(2, args.warmup // 4))
+    long_w = long_window_form(max(10, args.steps // 4), max(2, args.warmup // 4))
     mixed = mixed_case_form(max(10, args.steps // 4), max(2, args.warmup // 4))
     serve = serving(args.serving_seconds, 16.0) if args.serving_seconds > 0 else None
 
@@ -413,6 +449,7 @@ def main(argv=None):
         "cf16_over_cf32": forms["cf16"]["samples_per_s"] / f32["samples_per_s"],
         "read_probe_GBs": probe,
         "tf_window": tf,
+        "long_window": long_w,
         "mixed_case_cf16": mixed,
         "serving": serve,
         "flagged_frac": f32["flagged_frac"],

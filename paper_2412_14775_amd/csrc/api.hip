@@ -107,7 +107,8 @@ int validate(const rfi_params *p) {
   if ((int64_t)p->block_f * p->n_samples * sb >= (int64_t)1 << 31)
     return fail(RFI_ERR_INVALID_ARGUMENT, "block_f * n_samples * bytes per sample must be < 2^31");
   if ((p->options & RFI_OPT_PAPER_MIXED) &&
-      (p->vis_format != RFI_VIS_CF32 || rfi::windows_samples_per_lane(p->block_m, p->block_f) == 0))
+      rfi::kernel_for(p->block_m, p->block_f, p->vis_format == RFI_VIS_CF32 ? rfi::FMT_CF32 : rfi::FMT_CF16,
+                      true) != rfi::kWindows)
     return fail(RFI_ERR_UNSUPPORTED,
                 "RFI_OPT_PAPER_MIXED needs complex64 storage and a window M = K S (K <= 8, S a power of two, F S <= 64)");
   return RFI_OK;
@@ -117,11 +118,13 @@ int validate(const rfi_params *p) {
 // (window-aligned segments) so that small arrays still fill the GPU.
 int choose_segments(const rfi_params &p, int64_t n_streams) {
   int n_seg = 1;
-  if (p.block_f != 1 || (p.options & RFI_OPT_PAPER_MIXED)) return 1;
+  const rfi::KernelKind kind =
+      rfi::kernel_for(p.block_m, p.block_f, p.vis_format == RFI_VIS_CF32 ? rfi::FMT_CF32 : rfi::FMT_CF16,
+                      (p.options & RFI_OPT_PAPER_MIXED) != 0);
+  if (kind != rfi::kTiled && kind != rfi::kLong) return 1;  // only these kernels split a stream
   const int64_t target_waves = 64 * 1024;
   while (n_seg < rfi::kWavesPerBlock && n_streams * n_seg < target_waves &&
-         p.n_samples % (2 * n_seg * p.block_m) == 0 && p.n_samples / (2 * n_seg) >= 256 &&
-         rfi::tiled_supports(p.block_m))
+         p.n_samples % (2 * n_seg * p.block_m) == 0 && p.n_samples / (2 * n_seg) >= 256)
     n_seg *= 2;
   return n_seg;
 }

@@ -52,7 +52,16 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kMaxTiledLog2M = 12;  // tiled kernels exist for M = 2 .. 4096
 
-// Kernel selection.  Returns hipErrorInvalidValue when no kernel matches.
+// The kernel that screens windows of M samples x F channels in storage format `fmt`:
+// tiled (F = 1, M a power of two <= 4096), windowed (M = K S, K <= 8, S a power of two,
+// F S <= 64), long (F = 1, M at least one step: 256 complex64 / 512 complex-half samples),
+// otherwise one lane per window.  The paper's mixed precision exists only in the windowed
+// kernel with complex64 storage (kNone elsewhere).  The tiled and long kernels may split a
+// stream into window-aligned segments (one wave each).
+enum KernelKind { kTiled, kWindows, kLong, kGeneric, kNone };
+KernelKind kernel_for(int M, int F, int fmt, bool mixed);
+
+// Kernel selection (kernel_for).  Returns hipErrorInvalidValue when no kernel matches.
 hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream);
 bool tiled_supports(int M);
 // Samples per lane of the windowed kernel for (M, F), or 0 when it does not apply.

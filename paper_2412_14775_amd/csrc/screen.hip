@@ -1,11 +1,12 @@
 // screen.hip -- gfx950 kernels of the online energy + polarisation RFI screen
 // (arXiv 2412.14775, Section 2, Tables 1-2).
 //
-// Three kernels share the per-sample and per-window code below:
-//   screen_tiled    time-only windows of M = 2^k samples (the hot path);
+// Four kernels share the per-sample and per-window code below (kernel_for picks one):
+//   screen_tiled    time-only windows of M = 2^k <= 4096 samples (the hot path);
 //   screen_windows  windows of M = K S samples x F channels (non-power-of-two M and
 //                   the paper's time x frequency windows), optionally in the
 //                   paper's mixed precision (Tables 3-4);
+//   screen_long     time-only windows of at least one step, edges anywhere;
 //   screen_generic  any other shape, one lane per window.
 //
 // screen_tiled, one pass over the visibilities, bound by HBM bandwidth:
@@ -398,6 +399,116 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
   finish_stream<1>(a, acc, stream, seg, active, wave, lane, xfer);
 }
 
+// Windows of M >= one step of samples (K 64) of one channel, any M: the window
+// edges may fall anywhere inside a step, at most one per step.  Same loads and LDS
+// transpose as the tiled kernel; a step that lies inside the current window is
+// summed without per-sample tests, the step holding a window's last sample is
+// summed in two masked passes (the end of this window, then the start of the
+// next) around the window's reduction.  Each lane adds its step sums plainly for
+// kFold steps before folding them into the window sums, so no lane sums more than
+// kFold K samples in a row whatever M is.
+template <int FMT>
+__global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
+  constexpr int K = FMT == FMT_CF32 ? 4 : 8;
+  constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
+  constexpr int SPI = kWave * K;
+  constexpr int kFold = 16;
+
+  __shared__ u32x4 tile[kWavesPerBlock][kTilePieces];
+  __shared__ float xfer[kWavesPerBlock][kXfer];
+
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int64_t unit = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const int64_t stream = unit / a.n_seg;
+  const int seg = (int)(unit - stream * a.n_seg);
+  const bool active = stream < a.n_groups;
+
+  StreamAcc<1> acc{};
+  if (active) {
+    const Thresholds th = stream_thresholds(a, stream);
+    const uint8_t *base = a.vis + (stream * a.T + (int64_t)seg * a.seg_samples) * SB;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t *>(base), (short)0, a.seg_samples * SB, kRsrcWord3);
+    const int n_steps = (a.seg_samples + SPI - 1) / SPI;
+    const int64_t out_base = stream * a.nW + (int64_t)seg * a.seg_windows;
+    u32x4 *my_tile = tile[wave];
+
+    u32x4 buf[kPieces];
+    auto issue = [&](int step) {
+#pragma unroll
+      for (int i = 0; i < kPieces; ++i)
+        buf[i] = __builtin_bit_cast(
+            u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                       rsrc, (unsigned)(step * SPI * SB) + (unsigned)((i * kWave + lane) * 16), 0, kLoadStreaming));
+    };
+    auto sample = [&](int j, float ps[8], float pr[8]) {
+      float x[8];
+      if constexpr (FMT == FMT_CF32) {
+        const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[lds_slot(kPieces * lane + 2 * j)]);
+        const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[lds_slot(kPieces * lane + 2 * j + 1)]);
+        x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
+        x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
+      } else {
+        const f16x8 h = __builtin_bit_cast(f16x8, my_tile[lds_slot(kPieces * lane + j)]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
+      }
+      accumulate_sample(ps, pr, x, a.eps);
+    };
+
+    float ps[8] = {}, pr[8] = {};      // plain sums since the last fold
+    float ss[8] = {}, sr[1][8] = {};   // the current window's sums
+    int since_fold = 0;
+    auto fold = [&]() {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        ss[k] += ps[k];
+        sr[0][k] += pr[k];
+        ps[k] = pr[k] = 0.0f;
+      }
+      since_fold = 0;
+    };
+    int w = 0;                  // current window, counted from the segment start
+    int w_end = a.M;            // one past its last sample, from the segment start
+    issue(0);
+    for (int step = 0; step < n_steps; ++step) {
+      wave_lds_order();
+#pragma unroll
+      for (int i = 0; i < kPieces; ++i) my_tile[lds_slot(i * kWave + lane)] = buf[i];
+      wave_lds_order();
+      if (step + 1 < n_steps) issue(step + 1);
+
+      const int t0 = step * SPI + lane * K;  // this lane's first sample of the step
+      if ((step + 1) * SPI < w_end) {        // uniform: the step lies inside the window
+#pragma unroll
+        for (int j = 0; j < K; ++j) sample(j, ps, pr);
+      } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+          if (t0 + j < w_end) sample(j, ps, pr);
+        fold();
+        float tot[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) tot[k] = group_sum<kWave>(ss[k]);
+        finish_window<1>(a, th, tot, sr, out_base + w, w < a.seg_windows, lane == 0, acc);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ss[k] = sr[0][k] = 0.0f;
+        const int start = w_end;
+        ++w;
+        w_end += a.M;
+        if (w < a.seg_windows) {               // the rest of the step opens the next window
+#pragma unroll
+          for (int j = 0; j < K; ++j)
+            if (t0 + j >= start) sample(j, ps, pr);
+        }
+      }
+      if (++since_fold == kFold) fold();
+    }
+  }
+  finish_stream<1>(a, acc, stream, seg, active, wave, lane, xfer);
+}
+
 // ----------------------------------------------------------------------------- paper's mixed precision
 // Tables 3-4: per-sample groups and the SK moments in FP32; the sums of the unit
 // vectors, their squares, r and its comparison, and the SK ratio and its
@@ -708,6 +819,14 @@ hipError_t dispatch_tiled(int log2m, const ScreenArgs &a, hipStream_t stream) {
 }
 
 template <int FMT>
+hipError_t launch_long(const ScreenArgs &a, hipStream_t stream) {
+  const int64_t units = a.n_groups * a.n_seg;
+  const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL((screen_long<FMT>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, a);
+  return hipGetLastError();
+}
+
+template <int FMT>
 hipError_t launch_generic(const ScreenArgs &a, hipStream_t stream) {
   const int64_t blocks = (a.n_groups + kWavesPerBlock - 1) / kWavesPerBlock;
   const dim3 grid((unsigned)blocks), block(kBlock);
@@ -807,18 +926,30 @@ int windows_samples_per_lane(int M, int F) {
   return K;
 }
 
+KernelKind kernel_for(int M, int F, int fmt, bool mixed) {
+  if (mixed) return fmt == FMT_CF32 && windows_samples_per_lane(M, F) > 0 ? kWindows : kNone;
+  if (F == 1 && tiled_supports(M)) return kTiled;
+  if (windows_samples_per_lane(M, F) > 0) return kWindows;
+  if (F == 1 && M >= kWave * (fmt == FMT_CF32 ? 4 : 8)) return kLong;
+  return kGeneric;
+}
+
 hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream) {
-  if (a.options & kOptPaperMixed) {  // complex64 storage and a windowed shape (checked by the plan)
-    const int K = windows_samples_per_lane(a.M, a.F);
-    return fmt == FMT_CF32 && K > 0 ? launch_windows<FMT_CF32, true>(K, a, stream) : hipErrorInvalidValue;
+  const bool cf32 = fmt == FMT_CF32;
+  switch (kernel_for(a.M, a.F, fmt, (a.options & kOptPaperMixed) != 0)) {
+    case kTiled: {
+      const int l = ilog2_exact(a.M);
+      return cf32 ? dispatch_tiled<FMT_CF32>(l, a, stream) : dispatch_tiled<FMT_CF16>(l, a, stream);
+    }
+    case kWindows: {
+      const int K = windows_samples_per_lane(a.M, a.F);
+      if (a.options & kOptPaperMixed) return launch_windows<FMT_CF32, true>(K, a, stream);
+      return cf32 ? launch_windows<FMT_CF32, false>(K, a, stream) : launch_windows<FMT_CF16, false>(K, a, stream);
+    }
+    case kLong: return cf32 ? launch_long<FMT_CF32>(a, stream) : launch_long<FMT_CF16>(a, stream);
+    case kGeneric: return cf32 ? launch_generic<FMT_CF32>(a, stream) : launch_generic<FMT_CF16>(a, stream);
+    default: return hipErrorInvalidValue;
   }
-  const int l = ilog2_exact(a.M);
-  if (a.F == 1 && l >= 1 && l <= kMaxTiledLog2M)
-    return fmt == FMT_CF32 ? dispatch_tiled<FMT_CF32>(l, a, stream) : dispatch_tiled<FMT_CF16>(l, a, stream);
-  const int K = windows_samples_per_lane(a.M, a.F);
-  if (K > 0)
-    return fmt == FMT_CF32 ? launch_windows<FMT_CF32, false>(K, a, stream) : launch_windows<FMT_CF16, false>(K, a, stream);
-  return fmt == FMT_CF32 ? launch_generic<FMT_CF32>(a, stream) : launch_generic<FMT_CF16>(a, stream);
 }
 
 size_t probe_sink_floats() { return (size_t)kProbeBlocks * kWavesPerBlock; }

@@ -16,12 +16,14 @@ def _integration(i, N=2, C=8, T=1024):
     return synth.correlate(synth.make_voltages(sc))
 
 
-@pytest.mark.parametrize("fmt,M,F", [("cf32", 16, 1), ("cf16", 64, 1), ("cf32", 20, 1), ("cf16", 10, 2)])
-def test_adaptive_thresholds_follow_oracle_state(fmt, M, F):
+@pytest.mark.parametrize("fmt,M,F,T,n_warm", [("cf32", 16, 1, 1024, 80), ("cf16", 64, 1, 1024, 80),
+                                             ("cf32", 20, 1, 1280, 80), ("cf16", 10, 2, 1280, 80),
+                                             ("cf32", 300, 1, 1200, 8), ("cf16", 600, 1, 1200, 4)])
+def test_adaptive_thresholds_follow_oracle_state(fmt, M, F, T, n_warm):
     from paper_2412_14775_amd import rfi
-    B, C, T = 3, 8, 1280 if M in (10, 20) else 1024
+    B, C = 3, 8
     kw = dict(d=2.1, s_low=0.2, s_high=2.6, gamma=0.5, kappa_sk=3.0, kappa_ds=3.0,
-              n_warm=80, options=oracle.OPT_ADAPTIVE, F=F)
+              n_warm=n_warm, options=oracle.OPT_ADAPTIVE, F=F)
     op, rp = make_params(B, C, T, M, fmt, **kw)
     plan = rfi.Plan(rp)
     state = oracle.AdaptiveState((B, C // F))
@@ -31,7 +33,7 @@ def test_adaptive_thresholds_follow_oracle_state(fmt, M, F):
         ref_in = vis if fmt == "cf32" else synth.to_cf16(vis)
         gpu = run_gpu(plan, to_device(ref_in, fmt))
         th = state.thresholds(op)
-        warm_seen |= bool(np.any(state.n >= 80))
+        warm_seen |= bool(np.any(state.n >= n_warm))
         th_b = {k: np.asarray(v)[..., None] for k, v in th.items()}
         ref = oracle.screen(ref_in, op, th_b)
         compare(gpu, ref_in, op, TOL_F32, thresholds=th, ref=ref, label=f"adaptive {fmt} M={M} it={i}")

@@ -22,17 +22,19 @@ def _gpu():
 
 
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
-@pytest.mark.parametrize("M,n_windows", [(4096, 3), (8192, 2)])
-def test_longest_windows(fmt, M, n_windows):
+@pytest.mark.parametrize("M,F,n_windows", [(4096, 1, 3), (8192, 1, 2), (8192, 2, 2)])
+def test_longest_windows(fmt, M, F, n_windows):
     """M = 4096 is the longest window of the tiled kernel (several steps per window, segments);
-    M = 8192 goes to the one-lane-per-window kernel."""
+    M = 8192 of one channel goes to the long-window kernel, and over two channels (16384
+    samples per window) to the one-lane-per-window kernel, whose compensated sums keep the
+    error from growing with the window."""
     T = M * n_windows
-    vis = scene_vis(2, 2, T, seed=M + n_windows, duty=(300, 40))
+    vis = scene_vis(2, 2, T, seed=M + n_windows + F, duty=(300, 40))
     if fmt == "cf32":
-        op, gpu = screen_both(vis, M, **thresholds_for(M))
-        compare(gpu, vis, op, TOL_F32, label=f"cf32 M={M}")
+        op, gpu = screen_both(vis, M, F=F, **thresholds_for(M * F))
+        compare(gpu, vis, op, TOL_F32, label=f"cf32 M={M} F={F}")
     else:
-        check_cf16(vis, M, f"cf16 M={M}", **thresholds_for(M))
+        check_cf16(vis, M, f"cf16 M={M} F={F}", F=F, **thresholds_for(M * F))
 
 
 def _device_masked_mean(vis, flags, M):

@@ -124,6 +124,21 @@ def test_few_long_streams_split_over_waves(fmt, M, T):
         check_cf16(vis, M, f"segmented cf16 M={M} T={T}", **thresholds_for(M))
 
 
+@pytest.mark.parametrize("fmt", ["cf32", "cf16"])
+@pytest.mark.parametrize("M,T,N", [(300, 3000, 2), (600, 3000, 2), (1000, 3000, 2), (3000, 3000, 2),
+                                   (3072, 6144, 2), (768, 6144, 1), (8192, 16384, 1)])
+def test_long_windows(fmt, M, T, N):
+    """Windows of at least one step (256 complex64 / 512 complex-half samples) that are not powers
+    of two up to 4096: edges fall anywhere inside a step, steps are ragged at the stream end,
+    and few streams split over waves (M = 300 in complex half goes to the one-lane kernel)."""
+    vis = scene_vis(N, 2, T, seed=M + T, duty=(500, 60))
+    if fmt == "cf32":
+        op, gpu = screen_both(vis, M, **thresholds_for(M))
+        compare(gpu, vis, op, TOL_F32, label=f"long cf32 M={M} T={T}")
+    else:
+        check_cf16(vis, M, f"long cf16 M={M} T={T}", **thresholds_for(M))
+
+
 # ----------------------------------------------------------------------------- time x frequency windows
 
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
