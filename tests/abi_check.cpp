@@ -6,6 +6,7 @@
 #include <cstring>
 #include <vector>
 
+#include "internal.h"
 #include "rfi.h"
 
 static int failures = 0;
@@ -28,7 +29,28 @@ static rfi_params good() {
   return p;
 }
 
+// Which kernel screens which window shape (rfi::kernel_for): the plan's segment choice and the
+// launch both follow it.
+static void kernel_choice() {
+  using namespace rfi;
+  const int c32 = FMT_CF32, c16 = FMT_CF16;
+  EXPECT(kernel_for(2, 1, c32, false) == kTiled && kernel_for(64, 1, c16, false) == kTiled);
+  EXPECT(kernel_for(4096, 1, c32, false) == kTiled);
+  EXPECT(kernel_for(8192, 1, c32, false) == kLong && kernel_for(8192, 1, c16, false) == kLong);
+  EXPECT(kernel_for(10, 2, c16, false) == kWindows && kernel_for(5, 4, c32, false) == kWindows);
+  EXPECT(kernel_for(20, 1, c32, false) == kWindows && kernel_for(3, 1, c16, false) == kWindows);
+  EXPECT(kernel_for(64, 2, c32, false) == kWindows && kernel_for(384, 1, c32, false) == kWindows);
+  EXPECT(kernel_for(300, 1, c32, false) == kLong && kernel_for(300, 1, c16, false) == kGeneric);
+  EXPECT(kernel_for(600, 1, c16, false) == kLong && kernel_for(3000, 1, c16, false) == kLong);
+  EXPECT(kernel_for(100, 1, c32, false) == kGeneric && kernel_for(8192, 2, c32, false) == kGeneric);
+  EXPECT(kernel_for(1000, 2, c16, false) == kGeneric);
+  EXPECT(kernel_for(10, 2, c32, true) == kWindows && kernel_for(64, 1, c32, true) == kWindows);
+  EXPECT(kernel_for(10, 2, c16, true) == kNone && kernel_for(1024, 1, c32, true) == kNone);
+  EXPECT(kernel_for(100, 1, c32, true) == kNone);
+}
+
 int main() {
+  kernel_choice();
   rfi_plan *plan = reinterpret_cast<rfi_plan *>(0x1);
   EXPECT(rfi_plan_create(nullptr, 0, &plan) == RFI_ERR_INVALID_ARGUMENT && plan == nullptr);
   EXPECT(std::strlen(rfi_last_error()) > 0);
