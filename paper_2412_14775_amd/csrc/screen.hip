@@ -580,20 +580,23 @@ __device__ __forceinline__ float group_sum_rt(float v, int L) {
   return v;
 }
 
-// Windows of M = K S time samples x F channels, K <= 8, L = F S <= 64 lanes per
+// Windows of M = K S time samples x F channels, K <= 8, F S <= 64 lanes per
 // window (any M with such a factorisation, and every F > 1 shape the tiled kernel
-// does not take).  One wave per channel group.  Lane l = (j L + f S + s) owns the
-// K consecutive samples s of channel f of window j of the step, so a lane stays
-// on one channel and keeps one masked sum.  A step covers 64 / L windows: for
-// each channel a contiguous run of 64 K / F samples, loaded coalesced
-// (channel-major) into the wave's LDS tile and read back per lane.
-template <int FMT, int K, int F, bool MIXED>
+// does not take).  One wave per channel group.  A window owns L lanes, L = F S
+// rounded up to a power of two; lane l = (j L + f S + s) owns the K consecutive
+// samples s of channel f of window j of the step, so a lane stays on one channel
+// and keeps one masked sum.  A step covers 64 / L windows: for each channel a
+// contiguous run of their samples, loaded coalesced (channel-major) into the
+// wave's LDS tile and read back per lane.  When F S is not a power of two (GEN,
+// e.g. M = 100 = 4 x 25 on 32 lanes) the L - F S lanes left over in each group
+// neither read nor add, and the channel sums at the end are masked wave sums.
+template <int FMT, int K, int F, bool MIXED, bool GEN>
 __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
   constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
   constexpr int PPS = SB / 16;                  // 16-byte pieces per sample
   constexpr int P = K * PPS;                    // pieces per lane per step
-  constexpr int CH_PIECES = kWave * P / F;      // pieces of one channel per step
-  constexpr int CH_SAMPLES = kWave * K / F;     // samples of one channel per step
+  constexpr int CH_PIECES = kWave * P / F;      // pieces of one channel per step (F S = L)
+  constexpr int CH_SAMPLES = kWave * K / F;     // samples of one channel per step (F S = L)
   __shared__ u32x4 tile[kWavesPerBlock][kWave * P];
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -601,9 +604,15 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
   const int64_t group = (int64_t)blockIdx.x * kWavesPerBlock + wave;
   const bool active = group < a.n_groups;
   const int S = a.M / K;                        // lanes per channel of a window
-  const int L = F * S;                          // lanes per window
-  const int j = lane / L, f = (lane / S) % F, s = lane % S;
+  const int FS = F * S;                         // lanes that hold samples
+  int L = FS;                                   // lanes per window
+  if constexpr (GEN) L = 1 << (32 - __builtin_clz(FS - 1));
+  const int g = lane % L;
+  const bool act = !GEN || g < FS;              // lane holds samples
+  const int j = lane / L, f = act ? g / S : 0, s = act ? g % S : 0;
   const int wps = kWave / L;                    // windows per step
+  const int ch_samples = GEN ? wps * a.M : CH_SAMPLES;
+  const int ch_pieces = ch_samples * PPS;
 
   float acc[8] = {};
   float kept = 0.0f;
@@ -620,15 +629,17 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         const int q = i * kWave + lane;         // piece of the step, channel-major
-        const int ch = q / CH_PIECES, r = q % CH_PIECES;
-        // pieces past the end of the channel (ragged last step) belong to no valid window
-        const bool inside = step * CH_SAMPLES + r / PPS < a.T;
-        const unsigned off = (unsigned)(ch * a.T + step * CH_SAMPLES) * SB + (unsigned)(r * 16);  // may pass 2^31 when !inside
+        const int ch = GEN ? q / ch_pieces : q / CH_PIECES;
+        const int r = GEN ? q - ch * ch_pieces : q % CH_PIECES;
+        // pieces past the end of the channel (ragged last step) belong to no valid
+        // window, nor do those past the F channels of a GEN step
+        const bool inside = (!GEN || ch < F) && step * ch_samples + r / PPS < a.T;
+        const unsigned off = (unsigned)(ch * a.T + step * ch_samples) * SB + (unsigned)(r * 16);  // may pass 2^31 when !inside
         buf[i] = inside ? __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming))
                         : u32x4{0u, 0u, 0u, 0u};
       }
     };
-    const int my_piece = f * CH_PIECES + (j * S + s) * P;
+    const int my_piece = act ? f * ch_pieces + (j * S + s) * P : 0;
     issue(0);
     for (int step = 0; step < n_steps; ++step) {
       wave_lds_order();
@@ -639,6 +650,7 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
       float ws[8] = {}, wr[8] = {};
 #pragma unroll
       for (int k = 0; k < K; ++k) {
+        if (!act) break;                        // GEN: a lane left over in its group
         float x[8];
         if constexpr (FMT == FMT_CF32) {
           const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k]);
@@ -666,9 +678,9 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
       const float wr1[1][8] = {{wr[0], wr[1], wr[2], wr[3], wr[4], wr[5], wr[6], wr[7]}};
       if constexpr (MIXED) {
         Thresholds t16{round16(th.s_low), round16(th.s_high), round16(th.g_re), round16(th.g_im)};
-        finish_window<1, true>(a, t16, tot, wr1, group * a.nW + w, valid, lane % L == 0, one);
+        finish_window<1, true>(a, t16, tot, wr1, group * a.nW + w, valid, g == 0, one);
       } else {
-        finish_window<1>(a, th, tot, wr1, group * a.nW + w, valid, lane % L == 0, one);
+        finish_window<1>(a, th, tot, wr1, group * a.nW + w, valid, g == 0, one);
       }
 #pragma unroll
       for (int e = 0; e < 8; ++e) acc[e] += one.sum[0][e];
@@ -676,13 +688,21 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
       if (a.state != nullptr && one.mom.n > 0.0f) mom = moments_merge(mom, one.mom);
     }
   }
-  // masked sums: reduce over the lanes of each channel (skip the f bits of the lane index)
+  // masked sums: reduce over the lanes of each channel
+  float chan[GEN ? F : 1][8];
+  if constexpr (GEN) {                          // channel bits are not lane bits: masked wave sums
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    float v = acc[e];
-    for (int m = 1; m < kWave; m <<= 1)
-      if (m < S || m >= L) v += __shfl_xor(v, m);
-    acc[e] = v;
+    for (int c = 0; c < F; ++c)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) chan[c][e] = group_sum<64>(act && f == c ? acc[e] : 0.0f);
+  } else {                                      // skip the f bits of the lane index
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float v = acc[e];
+      for (int m = 1; m < kWave; m <<= 1)
+        if (m < S || m >= L) v += __shfl_xor(v, m);
+      chan[0][e] = v;
+    }
   }
   kept = group_sum<64>(kept);
   if (a.state != nullptr) {
@@ -690,13 +710,20 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
     for (int m = 1; m < kWave; m <<= 1) mom = moments_merge(mom, moments_shfl_xor(mom, m));
   }
   if (!active) return;
-  if (lane < L && s == 0) {                     // lane f S of window 0 writes channel f
-    const int64_t stream = group * F + f;
-    const float inv = kept > 0.0f ? 1.0f / kept : 0.0f;
+  const float inv = kept > 0.0f ? 1.0f / kept : 0.0f;
+  auto write_channel = [&](int c, const float v[8]) {
+    const int64_t stream = group * F + c;
     f32x4 *out = reinterpret_cast<f32x4 *>(a.avg + stream * 8);
-    out[0] = f32x4{acc[0] * inv, acc[1] * inv, acc[2] * inv, acc[3] * inv};
-    out[1] = f32x4{acc[4] * inv, acc[5] * inv, acc[6] * inv, acc[7] * inv};
+    out[0] = f32x4{v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv};
+    out[1] = f32x4{v[4] * inv, v[5] * inv, v[6] * inv, v[7] * inv};
     a.weight[stream] = kept * a.invT;
+  };
+  if constexpr (GEN) {
+    if (lane == 0)
+#pragma unroll
+      for (int c = 0; c < F; ++c) write_channel(c, chan[c]);
+  } else if (lane < L && s == 0) {              // lane f S of window 0 writes channel f
+    write_channel(f, chan[0]);
   }
   if (lane == 0 && a.state != nullptr && mom.n > 0.0f) {
     StateRec *st = reinterpret_cast<StateRec *>(a.state) + group;
@@ -842,29 +869,40 @@ hipError_t launch_generic(const ScreenArgs &a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int FMT, int K, bool MIXED>
+template <int FMT, int K, bool MIXED, bool GEN>
 hipError_t launch_windows_k(const ScreenArgs &a, hipStream_t stream) {
   const int64_t blocks = (a.n_groups + kWavesPerBlock - 1) / kWavesPerBlock;
   const dim3 grid((unsigned)blocks), block(kBlock);
   switch (a.F) {
-    case 1: hipLaunchKernelGGL((screen_windows<FMT, K, 1, MIXED>), grid, block, 0, stream, a); break;
-    case 2: hipLaunchKernelGGL((screen_windows<FMT, K, 2, MIXED>), grid, block, 0, stream, a); break;
-    case 4: hipLaunchKernelGGL((screen_windows<FMT, K, 4, MIXED>), grid, block, 0, stream, a); break;
+    case 1: hipLaunchKernelGGL((screen_windows<FMT, K, 1, MIXED, GEN>), grid, block, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((screen_windows<FMT, K, 2, MIXED, GEN>), grid, block, 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((screen_windows<FMT, K, 4, MIXED, GEN>), grid, block, 0, stream, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+// GEN (F S not a power of two) exists only outside the paper's mixed precision.
+template <int FMT, int K, bool MIXED>
+hipError_t launch_windows_g(bool gen, const ScreenArgs &a, hipStream_t stream) {
+  if constexpr (MIXED)
+    return gen ? hipErrorInvalidValue : launch_windows_k<FMT, K, true, false>(a, stream);
+  else
+    return gen ? launch_windows_k<FMT, K, false, true>(a, stream) : launch_windows_k<FMT, K, false, false>(a, stream);
+}
+
 template <int FMT, bool MIXED>
 hipError_t launch_windows(int K, const ScreenArgs &a, hipStream_t stream) {
+  const int FS = a.F * (a.M / K);
+  const bool gen = (FS & (FS - 1)) != 0;
   switch (K) {
-    case 2: return launch_windows_k<FMT, 2, MIXED>(a, stream);
-    case 3: return launch_windows_k<FMT, 3, MIXED>(a, stream);
-    case 4: return launch_windows_k<FMT, 4, MIXED>(a, stream);
-    case 5: return launch_windows_k<FMT, 5, MIXED>(a, stream);
-    case 6: return launch_windows_k<FMT, 6, MIXED>(a, stream);
-    case 7: return launch_windows_k<FMT, 7, MIXED>(a, stream);
-    case 8: return launch_windows_k<FMT, 8, MIXED>(a, stream);
+    case 2: return launch_windows_g<FMT, 2, MIXED>(gen, a, stream);
+    case 3: return launch_windows_g<FMT, 3, MIXED>(gen, a, stream);
+    case 4: return launch_windows_g<FMT, 4, MIXED>(gen, a, stream);
+    case 5: return launch_windows_g<FMT, 5, MIXED>(gen, a, stream);
+    case 6: return launch_windows_g<FMT, 6, MIXED>(gen, a, stream);
+    case 7: return launch_windows_g<FMT, 7, MIXED>(gen, a, stream);
+    case 8: return launch_windows_g<FMT, 8, MIXED>(gen, a, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -921,16 +959,32 @@ bool tiled_supports(int M) {
 }
 
 int windows_samples_per_lane(int M, int F) {
-  // largest power of two S dividing M with K = M / S <= 8, and F S <= 64 lanes per window
-  int S = 1;
-  while (M % (2 * S) == 0 && M / S > 8) S *= 2;
-  const int K = M / S;
-  if (K < 2 || K > 8 || F * S > kWave) return 0;
-  return K;
+  // K in 2..8 dividing M with F S <= 64 (S = M / K) that uses the largest share of the
+  // power-of-two lane group it needs, F S / L; among equals the largest K (fewer lanes,
+  // more samples per lane).  A factorisation with S a power of two uses all its lanes
+  // and wins whenever there is one.
+  int best = 0;
+  double best_use = 0.0;
+  for (int K = 8; K >= 2; --K) {
+    if (M % K != 0 || F * (M / K) > kWave) continue;
+    const int FS = F * (M / K);
+    int L = 1;
+    while (L < FS) L *= 2;
+    const double use = (double)FS / L;
+    if (use > best_use) {
+      best_use = use;
+      best = K;
+    }
+  }
+  return best;
 }
 
 KernelKind kernel_for(int M, int F, int fmt, bool mixed) {
-  if (mixed) return fmt == FMT_CF32 && windows_samples_per_lane(M, F) > 0 ? kWindows : kNone;
+  if (mixed) {  // the windowed kernel with whole power-of-two lane groups, complex64 storage
+    const int K = windows_samples_per_lane(M, F);
+    const int FS = K > 0 ? F * (M / K) : 0;
+    return fmt == FMT_CF32 && K > 0 && (FS & (FS - 1)) == 0 ? kWindows : kNone;
+  }
   if (F == 1 && tiled_supports(M)) return kTiled;
   if (windows_samples_per_lane(M, F) > 0) return kWindows;
   if (F == 1 && M >= kWave * (fmt == FMT_CF32 ? 4 : 8)) return kLong;

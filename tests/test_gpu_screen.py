@@ -139,6 +139,21 @@ def test_long_windows(fmt, M, T, N):
         check_cf16(vis, M, f"long cf16 M={M} T={T}", **thresholds_for(M))
 
 
+@pytest.mark.parametrize("fmt", ["cf32", "cf16"])
+@pytest.mark.parametrize("M,F,C,T", [(100, 1, 2, 1000), (300, 1, 2, 3000), (50, 1, 2, 1000), (15, 2, 4, 600),
+                                     (9, 2, 4, 450), (25, 4, 8, 500), (100, 2, 4, 1000)])
+def test_windows_on_partial_lane_groups(fmt, M, F, C, T):
+    """Windows whose F S lanes are not a power of two (M = 100 = 4 x 25 on 32 lanes, 300 = 5 x 60
+    on 64, 15 x 2 = 5 x (3 x 2) on 8, ...): the left-over lanes of each group must neither read
+    nor add, and the channel sums are masked wave sums."""
+    vis = scene_vis(2, C, T, seed=M * 10 + F, duty=(120, 25))
+    if fmt == "cf32":
+        op, gpu = screen_both(vis, M, F=F, **thresholds_for(M * F))
+        compare(gpu, vis, op, TOL_F32, label=f"partial groups cf32 {M}x{F}")
+    else:
+        check_cf16(vis, M, f"partial groups cf16 {M}x{F}", F=F, **thresholds_for(M * F))
+
+
 # ----------------------------------------------------------------------------- time x frequency windows
 
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
