@@ -409,8 +409,8 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
 // summed in two masked passes (the end of this window, then the start of the
 // next) around the window's reduction.  Each lane adds its step sums plainly for
 // kFold steps before folding them into the window sums, so no lane sums more than
-// kFold K samples in a row whatever M is.
-template <int FMT>
+// kFold K samples in a row whatever M is.  PIN_EDGES: see sample() below.
+template <int FMT, bool PIN_EDGES>
 __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
   constexpr int K = FMT == FMT_CF32 ? 4 : 8;
   constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
@@ -445,7 +445,7 @@ __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
             u32x4, __builtin_amdgcn_raw_buffer_load_b128(
                        rsrc, (unsigned)(step * SPI * SB) + (unsigned)((i * kWave + lane) * 16), 0, kLoadStreaming));
     };
-    auto sample = [&](int j, float ps[8], float pr[8]) {
+    auto sample = [&](int j, float ps[8], float pr[8], bool edge) {
       float x[8];
       if constexpr (FMT == FMT_CF32) {
         const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[lds_slot(kPieces * lane + 2 * j)]);
@@ -458,6 +458,15 @@ __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
         for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
       }
       accumulate_sample(ps, pr, x, a.eps);
+      // In the masked passes of an edge step the compiler keeps the converted samples
+      // alive for the raw sums (180 VGPRs for complex half); adding the raw sums at once
+      // there (154 VGPRs) is 12-15 % faster for complex half when edges are frequent
+      // (M = 600, 1000) and 3 % slower when they are rare (M = 3072), so the launch asks
+      // for it only for complex half with M < 2048.  Complex64 is the same either way.
+      if (PIN_EDGES && edge) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) asm volatile("" : "+v"(pr[k]));
+      }
     };
 
     float ps[8] = {}, pr[8] = {};      // plain sums since the last fold
@@ -485,11 +494,11 @@ __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
       const int t0 = step * SPI + lane * K;  // this lane's first sample of the step
       if ((step + 1) * SPI < w_end) {        // uniform: the step lies inside the window
 #pragma unroll
-        for (int j = 0; j < K; ++j) sample(j, ps, pr);
+        for (int j = 0; j < K; ++j) sample(j, ps, pr, false);
       } else {
 #pragma unroll
         for (int j = 0; j < K; ++j)
-          if (t0 + j < w_end) sample(j, ps, pr);
+          if (t0 + j < w_end) sample(j, ps, pr, true);
         fold();
         float tot[8];
 #pragma unroll
@@ -503,7 +512,7 @@ __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
         if (w < a.seg_windows) {               // the rest of the step opens the next window
 #pragma unroll
           for (int j = 0; j < K; ++j)
-            if (t0 + j >= start) sample(j, ps, pr);
+            if (t0 + j >= start) sample(j, ps, pr, true);
         }
       }
       if (++since_fold == kFold) fold();
@@ -852,7 +861,13 @@ template <int FMT>
 hipError_t launch_long(const ScreenArgs &a, hipStream_t stream) {
   const int64_t units = a.n_groups * a.n_seg;
   const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL((screen_long<FMT>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, a);
+  if constexpr (FMT == FMT_CF16) {
+    if (a.M < 2048) {
+      hipLaunchKernelGGL((screen_long<FMT, true>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, a);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((screen_long<FMT, false>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, a);
   return hipGetLastError();
 }
 
