@@ -352,6 +352,11 @@ def serving(seconds: float, rate: float):
     }
 
 
+def progress(msg: str) -> None:
+    """One line per stage on stderr (stdout carries only the JSON result line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +374,8 @@ def main(argv=None):
     scene = synth.scene_fp32_baseline(SEED, N_STATIONS, N_CHANNELS, N_SAMPLES)
     e = synth.make_voltages(scene)                                # [N, C, T, 2] complex64
     cpu = None if args.no_cpu_baseline else cpu_baseline(e)
+    if cpu is not None:
+        progress(f"cpu baseline: {cpu['value']:.3g} samples/s ({cpu['sample']})")
 
     import torch
     from paper_2412_14775_amd import rfi
@@ -409,14 +416,21 @@ def main(argv=None):
             "flagged_frac": flagged,
             "host_wall_s": wall,
         }
+        progress(f"{name}: {forms[name]['samples_per_s']:.4g} samples/s, {forms[name]['achieved_GBs']:.0f} GB/s")
     probe = probe_bandwidth(vis32, vis32.numel() * 4, stream)
     copy_calibration(vis32, stream)
     del vis32, vis16
     torch.cuda.empty_cache()
+    progress(f"read probe: {probe:.0f} GB/s")
     tf = tf_window_form(max(10, args.steps // 4), max(2, args.warmup // 4))
+    progress("10 x 2 windows done")
     long_w = long_window_form(max(10, args.steps // 4), max(2, args.warmup // 4))
+    progress("one-window-per-integration form done")
     mixed = mixed_case_form(max(10, args.steps // 4), max(2, args.warmup // 4))
+    progress("64-station mixed case done")
     serve = serving(args.serving_seconds, 16.0) if args.serving_seconds > 0 else None
+    if serve is not None:
+        progress(f"serving: p99 {serve['p99_ms']:.2f} ms")
 
     f32 = forms["cf32"]
     digest = kernel_source_digest()
