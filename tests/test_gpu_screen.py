@@ -129,8 +129,9 @@ def test_few_long_streams_split_over_waves(fmt, M, T):
                                    (3072, 6144, 2), (768, 6144, 1), (8192, 16384, 1)])
 def test_long_windows(fmt, M, T, N):
     """Windows of at least one step (256 complex64 / 512 complex-half samples) that are not powers
-    of two up to 4096: edges fall anywhere inside a step, steps are ragged at the stream end,
-    and few streams split over waves (M = 300 in complex half goes to the one-lane kernel)."""
+    of two up to 4096 and have no factor K <= 8 with S <= 64 (the long-window kernel): edges fall
+    anywhere inside a step, steps are ragged at the stream end, and few streams split over waves.
+    M = 300 (5 x 60) goes to the windowed kernel instead and stays here as a cross-check."""
     vis = scene_vis(N, 2, T, seed=M + T, duty=(500, 60))
     if fmt == "cf32":
         op, gpu = screen_both(vis, M, **thresholds_for(M))
