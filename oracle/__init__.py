@@ -31,9 +31,12 @@ forms of the SK estimator's mean and variance for Gamma-distributed inputs
 (Nita & Gary 2010, cited in Section 2.1), hand-derived worked windows,
 isotropic-null moments of the directional statistic, SU(2) invariance,
 brute-force flag tables, library cross-checks of the averaging and of the
-running mean/variance.  The adaptive-threshold extension is pinned only
-against NumPy's own mean/variance of the same windows ("parity unpinned" with
-respect to the paper, which gives no formula for it).
+running mean/variance.  The adaptive-threshold extension's running state is
+pinned against NumPy's mean/variance of the same windows and against the
+closed-form null moments it must converge to (tau: mean 1 and the Nita & Gary
+variance; r: E r^2 = 1/M for isotropic directions); its threshold rule
+(mean -/+ kappa sigma) is a reading of the paper's future-work remark, which
+gives no formula.
 """
 from .mixed import mixed_window_stats, screen_mixed  # noqa: F401
 from .screen import (  # noqa: F401

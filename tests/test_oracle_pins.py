@@ -404,6 +404,37 @@ def test_adaptive_state_matches_numpy_moments():
     np.testing.assert_allclose(th["gamma_im"], state.mean[..., 2] + np.float32(2.0) * sd[..., 2])
 
 
+@pytest.mark.parametrize("M", [16, 64])
+def test_adaptive_state_converges_to_null_moments(M):
+    """The running state against closed forms rather than numpy: unpolarized dual-pol voltages
+    (xx = |x|^2, xy = x y*, yx = y x*, yy = |y|^2 with x, y circular Gaussian) give |I| ~ Gamma(2),
+    so with d = 2 the state's tau mean tends to 1 and its variance to the Nita & Gary closed form;
+    each sample's Re(Q, U, V) has length |I| and a direction uniform on the sphere, so
+    E[r_re^2] = E|sum of M unit vectors|^2 / M^2 = 1/M exactly (mean^2 + variance of the state).
+    Five integrations, nothing flagged (loose plan thresholds, adaptive ones never engaged)."""
+    rng = np.random.default_rng(700 + M)
+    n_int, n_win = 5, 8000
+    params = Params(M=M, d=2.0, s_low=-10.0, s_high=100.0, gamma=1.5,
+                    n_warm=10 ** 9, options=oracle.OPT_ADAPTIVE)
+    state = oracle.AdaptiveState((1,))
+    for _ in range(n_int):
+        x, y = _cn(rng, (1, n_win * M)), _cn(rng, (1, n_win * M))
+        xy = x * np.conj(y)
+        vis = np.stack([np.abs(x) ** 2, xy, np.conj(xy), np.abs(y) ** 2], axis=-1)
+        out = oracle.screen_adaptive(vis, params, state)
+        assert not out["flags"].any()
+    n = n_int * n_win
+    assert state.n[0] == n
+    var_tau = _sk_var_gamma(2, M)
+    mean, var = state.mean[0], state.m2[0] / (n - 1)
+    assert abs(mean[0] - 1.0) < 4 * math.sqrt(var_tau / n), mean[0]
+    assert abs(var[0] / var_tau - 1.0) < 0.06, (var[0], var_tau)
+    r2 = mean[1] ** 2 + var[1] * (n - 1) / n                # sample mean of r_re^2
+    se_r2 = math.sqrt(2.0 / 3.0 / n) / M                    # |S|^2 ~ (M/3) chi2_3 for large M
+    assert abs(r2 - 1.0 / M) < 4 * se_r2, (r2, 1.0 / M)
+    assert state.mean[0, 2] == 0.0 and state.m2[0, 2] == 0.0   # autocorrelation-like: Im parts vanish
+
+
 def test_adaptive_state_cold_uses_plan_thresholds():
     params = Params(M=16, s_low=0.25, s_high=2.5, gamma=0.5, n_warm=1000)
     state = oracle.AdaptiveState((4,))
