@@ -404,13 +404,15 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
 
 // Windows of M >= one step of samples (K 64) of one channel, any M: the window
 // edges may fall anywhere inside a step, at most one per step.  Same loads and LDS
-// transpose as the tiled kernel; a step that lies inside the current window is
-// summed without per-sample tests, the step holding a window's last sample is
-// summed in two masked passes (the end of this window, then the start of the
-// next) around the window's reduction.  Each lane adds its step sums plainly for
-// kFold steps before folding them into the window sums, so no lane sums more than
-// kFold K samples in a row whatever M is.  PIN_EDGES: see sample() below.
-template <int FMT, bool PIN_EDGES>
+// transpose as the tiled kernel; a step that lies inside the current window, or
+// ends exactly where it does, is summed without per-sample tests.  In a step with
+// an edge inside it the lanes take runs of K + 1 samples that do not cross the
+// edge: the first lanes the samples that close this window, the others those that
+// open the next (66 K / (K+1) lanes at most), so the step costs K + 1 sample slots
+// instead of the 2 K of two masked passes over every lane.  Each lane adds its
+// step sums plainly for kFold steps before folding them into the window sums, so
+// no lane sums more than kFold K samples in a row whatever M is.
+template <int FMT>
 __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
   constexpr int K = FMT == FMT_CF32 ? 4 : 8;
   constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
@@ -445,28 +447,20 @@ __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
             u32x4, __builtin_amdgcn_raw_buffer_load_b128(
                        rsrc, (unsigned)(step * SPI * SB) + (unsigned)((i * kWave + lane) * 16), 0, kLoadStreaming));
     };
-    auto sample = [&](int j, float ps[8], float pr[8], bool edge) {
+    // sample t of the step (t = K lane + j in the plain steps), from the LDS tile
+    auto sample = [&](int t, float ps[8], float pr[8]) {
       float x[8];
       if constexpr (FMT == FMT_CF32) {
-        const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[lds_slot(kPieces * lane + 2 * j)]);
-        const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[lds_slot(kPieces * lane + 2 * j + 1)]);
+        const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[lds_slot(2 * t)]);
+        const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[lds_slot(2 * t + 1)]);
         x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
         x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
       } else {
-        const f16x8 h = __builtin_bit_cast(f16x8, my_tile[lds_slot(kPieces * lane + j)]);
+        const f16x8 h = __builtin_bit_cast(f16x8, my_tile[lds_slot(t)]);
 #pragma unroll
         for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
       }
       accumulate_sample(ps, pr, x, a.eps);
-      // In the masked passes of an edge step the compiler keeps the converted samples
-      // alive for the raw sums (180 VGPRs for complex half); adding the raw sums at once
-      // there (154 VGPRs) is 12-15 % faster for complex half when edges are frequent
-      // (M = 600, 1000) and 3 % slower when they are rare (M = 3072), so the launch asks
-      // for it only for complex half with M < 2048.  Complex64 is the same either way.
-      if (PIN_EDGES && edge) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) asm volatile("" : "+v"(pr[k]));
-      }
     };
 
     float ps[8] = {}, pr[8] = {};      // plain sums since the last fold
@@ -491,14 +485,7 @@ __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
       wave_lds_order();
       if (step + 1 < n_steps) issue(step + 1);
 
-      const int t0 = step * SPI + lane * K;  // this lane's first sample of the step
-      if ((step + 1) * SPI < w_end) {        // uniform: the step lies inside the window
-#pragma unroll
-        for (int j = 0; j < K; ++j) sample(j, ps, pr, false);
-      } else {
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-          if (t0 + j < w_end) sample(j, ps, pr, true);
+      auto close_window = [&]() {            // window w ends in this step: reduce, finish
         fold();
         float tot[8];
 #pragma unroll
@@ -506,13 +493,36 @@ __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
         finish_window<1>(a, th, tot, sr, out_base + w, w < a.seg_windows, lane == 0, acc);
 #pragma unroll
         for (int k = 0; k < 8; ++k) ss[k] = sr[0][k] = 0.0f;
-        const int start = w_end;
         ++w;
         w_end += a.M;
-        if (w < a.seg_windows) {               // the rest of the step opens the next window
+      };
+      const int n1 = w_end - step * SPI;     // samples of the step in window w (uniform)
+      if (n1 >= SPI) {                       // the step lies inside the window, or ends it
 #pragma unroll
-          for (int j = 0; j < K; ++j)
-            if (t0 + j >= start) sample(j, ps, pr, true);
+        for (int j = 0; j < K; ++j) sample(lane * K + j, ps, pr);
+        if (n1 == SPI) close_window();
+      } else {
+        constexpr int C = K + 1;               // samples per lane in an edge step
+        const int c1 = (n1 + C - 1) / C;       // lanes that take the n1 closing samples
+        const bool closing = lane < c1;
+        const int lo = closing ? lane * C : n1 + (lane - c1) * C;
+        const int hi = min(lo + C, closing ? n1 : SPI);
+        float cs[8] = {}, cr[8] = {};
+#pragma unroll
+        for (int j = 0; j < C; ++j)
+          if (lo + j < hi) sample(lo + j, cs, cr);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          ps[k] += closing ? cs[k] : 0.0f;
+          pr[k] += closing ? cr[k] : 0.0f;
+        }
+        close_window();
+        if (w < a.seg_windows) {               // the other lanes' runs open the next window
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            ps[k] = closing ? 0.0f : cs[k];
+            pr[k] = closing ? 0.0f : cr[k];
+          }
         }
       }
       if (++since_fold == kFold) fold();
@@ -857,17 +867,19 @@ hipError_t dispatch_tiled(int log2m, const ScreenArgs &a, hipStream_t stream) {
   }
 }
 
+// Unused dynamic LDS that caps the complex-half long-window kernel at two blocks (8 waves)
+// per CU (33 KiB static + 22 KiB > 160 KiB / 3) where edge steps are rare (M >= 2048): its
+// plain steps then stream faster than at the three blocks its registers allow (M = 3072:
+// 0.82 -> 0.87 of the HBM peak).  With frequent edges (M = 600-1000) three blocks are better
+// (two: -16 to -18 %), and complex64 is the same either way.
+constexpr unsigned kLongCf16RareEdgePad = 22528;
+
 template <int FMT>
 hipError_t launch_long(const ScreenArgs &a, hipStream_t stream) {
   const int64_t units = a.n_groups * a.n_seg;
   const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
-  if constexpr (FMT == FMT_CF16) {
-    if (a.M < 2048) {
-      hipLaunchKernelGGL((screen_long<FMT, true>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, a);
-      return hipGetLastError();
-    }
-  }
-  hipLaunchKernelGGL((screen_long<FMT, false>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, a);
+  const unsigned pad = FMT == FMT_CF16 && a.M >= 2048 ? kLongCf16RareEdgePad : 0u;
+  hipLaunchKernelGGL((screen_long<FMT>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
   return hipGetLastError();
 }
 
