@@ -176,6 +176,16 @@ int rfi_probe_read(const void *src, size_t bytes, float *sink, void *hip_stream)
  * calibrate hardware byte counters. */
 int rfi_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 
+/* Device check of the complex-half sample sums: the windowed and long-window kernels form
+ * the sums and differences of binary16 parts in one v_fma_mix_f32 each, which must equal
+ * conversion to float32 followed by a float32 add, bit for bit.  Every binary16 value a is
+ * taken against 1024 values b (signed zeros, subnormals, the largest finite values,
+ * infinities, a NaN, pseudo-random patterns) in each form the kernels use; mismatches[a]
+ * (device, 65536 uint32, written by the call) counts the differences, NaN results comparing
+ * equal.  All zero means the kernels' complex-half sums are those of the plain definition.
+ * Asynchronous on hip_stream.  Errors: RFI_ERR_INVALID_ARGUMENT for NULL. */
+int rfi_probe_half_sums(uint32_t *mismatches, void *hip_stream);
+
 /* ------------------------------------------------------------------------------------------
  * Hyperparameters (Section 2.3): the thresholds follow from a desired false-alarm
  * probability, and small windows need fine-tuning on RFI-free data.  Host functions, no

@@ -327,4 +327,10 @@ int rfi_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream) {
   return e == hipSuccess ? ok() : hip_fail(e, "probe_copy launch");
 }
 
+int rfi_probe_half_sums(uint32_t *mismatches, void *hip_stream) {
+  if (mismatches == nullptr) return fail(RFI_ERR_INVALID_ARGUMENT, "mismatches must not be NULL");
+  hipError_t e = rfi::launch_probe_half_sums(mismatches, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? ok() : hip_fail(e, "probe_half_sums launch");
+}
+
 }  // extern "C"

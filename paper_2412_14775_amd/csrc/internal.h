@@ -73,5 +73,10 @@ int set_error(int code, const char *fmt, ...);
 hipError_t launch_probe_read(const void *src, size_t bytes, float *sink, hipStream_t stream);
 hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t stream);
 size_t probe_sink_floats();
+// Check of the complex-half sums against conversion + float32 add: one count per binary16
+// value (kHalfSumsValues entries of `bad`), each over kHalfSumsOthers second operands.
+constexpr int kHalfSumsValues = 65536;
+constexpr int kHalfSumsOthers = 1024;
+hipError_t launch_probe_half_sums(uint32_t *bad, hipStream_t stream);
 
 }  // namespace rfi

@@ -150,15 +150,10 @@ __device__ __forceinline__ Thresholds stream_thresholds(const ScreenArgs &a, int
   return t;
 }
 
-// One sample: Stokes (eq. IQUV) and the per-sample terms of Tables 1 and 2,
-// added to the window sums ws = (S1, S2, sum q^, u^, v^ of Re, of Im) and the
-// raw sums wr.  x = (xx_re, xx_im, xy_re, xy_im, yx_re, yx_im, yy_re, yy_im).
-__device__ __forceinline__ void accumulate_sample(float ws[8], float wr[8], const float x[8],
-                                                  float eps) {
-  const float Ir = x[0] + x[6], Ii = x[1] + x[7];
-  const float Qr = x[0] - x[6], Qi = x[1] - x[7];
-  const float Ur = x[2] + x[4], Ui = x[3] + x[5];
-  const float Vr = x[5] - x[3], Vi = x[2] - x[4];  // V = j (xy - yx)
+// Per-sample terms of Tables 1 and 2 from one sample's Stokes parameters (eq. IQUV),
+// added to the window sums ws = (S1, S2, sum q^, u^, v^ of Re, of Im).
+__device__ __forceinline__ void accumulate_stokes(float ws[8], float Ir, float Ii, float Qr, float Qi,
+                                                  float Ur, float Ui, float Vr, float Vi, float eps) {
   const float y = Ir * Ir + Ii * Ii;
   ws[0] += hw_sqrt(y);
   ws[1] += y;
@@ -170,8 +165,54 @@ __device__ __forceinline__ void accumulate_sample(float ws[8], float wr[8], cons
   ws[5] += Qi * ri;
   ws[6] += Ui * ri;
   ws[7] += Vi * ri;
+}
+
+// One sample: Stokes parameters and the per-sample terms into ws, the sample itself
+// into the raw sums wr.  x = (xx_re, xx_im, xy_re, xy_im, yx_re, yx_im, yy_re, yy_im).
+__device__ __forceinline__ void accumulate_sample(float ws[8], float wr[8], const float x[8],
+                                                  float eps) {
+  accumulate_stokes(ws, x[0] + x[6], x[1] + x[7], x[0] - x[6], x[1] - x[7], x[2] + x[4], x[3] + x[5],
+                    x[5] - x[3], x[2] - x[4], eps);  // I, Q, U, V = j (xy - yx)
 #pragma unroll
   for (int k = 0; k < 8; ++k) wr[k] += x[k];
+}
+
+// Sums and differences of binary16 halves of 32-bit words (half 0 = the low one) in
+// float32 with one rounding, by v_fma_mix_f32, which takes binary16 operands converted
+// exactly: mix_add<SA, SB>(a, b) == (float)a_SA + (float)b_SB bit for bit, and so on.
+template <int SA, int SB>
+__device__ __forceinline__ float mix_add(uint32_t a, uint32_t b) {
+  float d;
+  asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[%3,0,%4] op_sel_hi:[1,0,1]" : "=v"(d) : "v"(a), "v"(b), "n"(SA), "n"(SB));
+  return d;
+}
+template <int SA, int SB>
+__device__ __forceinline__ float mix_sub(uint32_t a, uint32_t b) {  // a_SA - b_SB
+  float d;
+  asm("v_fma_mix_f32 %0, %2, -1.0, %1 op_sel:[%4,0,%3] op_sel_hi:[1,0,1]" : "=v"(d) : "v"(a), "v"(b), "n"(SA), "n"(SB));
+  return d;
+}
+template <int SA>
+__device__ __forceinline__ float mix_acc(float acc, uint32_t a) {  // acc + a_SA
+  asm("v_fma_mix_f32 %0, %1, 1.0, %0 op_sel:[%2,0,0] op_sel_hi:[1,0,0]" : "+v"(acc) : "v"(a), "n"(SA));
+  return acc;
+}
+
+// accumulate_sample for a complex-half sample as it sits in memory (words xx, xy, yx,
+// yy; real part in the low half), without separate conversions: the same float32
+// results bit for bit, with 8 fewer VALU operations per sample.
+__device__ __forceinline__ void accumulate_sample_h(float ws[8], float wr[8], u32x4 h, float eps) {
+  accumulate_stokes(ws, mix_add<0, 0>(h.x, h.w), mix_add<1, 1>(h.x, h.w), mix_sub<0, 0>(h.x, h.w),
+                    mix_sub<1, 1>(h.x, h.w), mix_add<0, 0>(h.y, h.z), mix_add<1, 1>(h.y, h.z),
+                    mix_sub<1, 1>(h.z, h.y), mix_sub<0, 0>(h.y, h.z), eps);
+  wr[0] = mix_acc<0>(wr[0], h.x);
+  wr[1] = mix_acc<1>(wr[1], h.x);
+  wr[2] = mix_acc<0>(wr[2], h.y);
+  wr[3] = mix_acc<1>(wr[3], h.y);
+  wr[4] = mix_acc<0>(wr[4], h.z);
+  wr[5] = mix_acc<1>(wr[5], h.z);
+  wr[6] = mix_acc<0>(wr[6], h.w);
+  wr[7] = mix_acc<1>(wr[7], h.w);
 }
 
 // Per-stream running results of a wave.  A window covers F adjacent channels
@@ -449,18 +490,14 @@ __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
     };
     // sample t of the step (t = K lane + j in the plain steps), from the LDS tile
     auto sample = [&](int t, float ps[8], float pr[8]) {
-      float x[8];
       if constexpr (FMT == FMT_CF32) {
         const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[lds_slot(2 * t)]);
         const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[lds_slot(2 * t + 1)]);
-        x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
-        x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
+        const float x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        accumulate_sample(ps, pr, x, a.eps);
       } else {
-        const f16x8 h = __builtin_bit_cast(f16x8, my_tile[lds_slot(t)]);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
+        accumulate_sample_h(ps, pr, my_tile[lds_slot(t)], a.eps);
       }
-      accumulate_sample(ps, pr, x, a.eps);
     };
 
     float ps[8] = {}, pr[8] = {};      // plain sums since the last fold
@@ -670,21 +707,18 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (!act) break;                        // GEN: a lane left over in its group
-        float x[8];
         if constexpr (FMT == FMT_CF32) {
           const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k]);
           const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k + 1]);
-          x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
-          x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
+          const float x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+          if constexpr (MIXED)
+            accumulate_sample_mixed(ws, wr, x, a.eps);
+          else
+            accumulate_sample(ws, wr, x, a.eps);
         } else {
-          const f16x8 h = __builtin_bit_cast(f16x8, my_tile[my_piece + k]);
-#pragma unroll
-          for (int e = 0; e < 8; ++e) x[e] = (float)h[e];
+          static_assert(!MIXED, "the paper's mixed precision takes complex64 input");
+          accumulate_sample_h(ws, wr, my_tile[my_piece + k], a.eps);
         }
-        if constexpr (MIXED)
-          accumulate_sample_mixed(ws, wr, x, a.eps);
-        else
-          accumulate_sample(ws, wr, x, a.eps);
       }
       float tot[8];
 #pragma unroll
@@ -1036,6 +1070,50 @@ hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream) {
   }
 }
 
+// ----------------------------------------------------------------------------- half sums check
+
+__device__ __forceinline__ float cvt_f16_lo(uint32_t w) {  // binary16 in the low half -> float32
+  float f;
+  asm volatile("v_cvt_f32_f16 %0, %1" : "=v"(f) : "v"(w));
+  return f;
+}
+
+__device__ __forceinline__ bool same_f32(float x, float y) {
+  return (x != x && y != y) || __float_as_uint(x) == __float_as_uint(y);
+}
+
+// One thread per binary16 value a (65536 threads): every form of the complex-half sums
+// (mix_add, mix_sub, mix_acc, both halves) against conversion by v_cvt_f32_f16 followed by
+// a float32 add, for kHalfSumsOthers values b (signed zeros, subnormals, the largest finite
+// values, infinities, a NaN, then pseudo-random bit patterns).  bad[a] counts differences.
+__global__ void __launch_bounds__(kBlock) probe_half_sums_kernel(uint32_t *bad) {
+#pragma clang fp contract(off)  // the references below are single roundings: no fused c + a
+  const uint32_t a16 = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t special[] = {0x0000u, 0x8000u, 0x0001u, 0x8001u, 0x03ffu, 0x0400u, 0x3c00u, 0xbc00u,
+                              0x7bffu, 0xfbffu, 0x7c00u, 0xfc00u, 0x7e00u, 0x3555u, 0xb555u, 0x1000u};
+  uint32_t n = 0, x = 12345u;
+  for (int i = 0; i < kHalfSumsOthers; ++i) {
+    uint32_t b16;
+    if (i < 16) {
+      b16 = special[i];
+    } else {
+      x = x * 1664525u + 1013904223u;
+      b16 = x >> 16;
+    }
+    const uint32_t A = a16 | (b16 << 16), B = b16 | (a16 << 16);  // a low, b high; and swapped
+    const float fa = cvt_f16_lo(a16), fb = cvt_f16_lo(b16);
+    const float c1 = fb * 3.0f, c2 = fa * 0.37f;
+    n += !same_f32(mix_add<0, 0>(A, B), fa + fb);
+    n += !same_f32(mix_add<1, 1>(A, B), fb + fa);
+    n += !same_f32(mix_sub<0, 0>(A, B), fa - fb);
+    n += !same_f32(mix_sub<1, 1>(A, B), fb - fa);
+    n += !same_f32(mix_sub<0, 1>(A, A), fa - fb);
+    n += !same_f32(mix_acc<0>(c1, A), c1 + fa);
+    n += !same_f32(mix_acc<1>(c2, A), c2 + fb);
+  }
+  bad[a16] = n;
+}
+
 size_t probe_sink_floats() { return (size_t)kProbeBlocks * kWavesPerBlock; }
 
 hipError_t launch_probe_read(const void *src, size_t bytes, float *sink, hipStream_t stream) {
@@ -1047,6 +1125,11 @@ hipError_t launch_probe_read(const void *src, size_t bytes, float *sink, hipStre
 hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t stream) {
   hipLaunchKernelGGL(probe_copy_kernel, dim3(kProbeBlocks), dim3(kBlock), 0, stream,
                      static_cast<u32x4 *>(dst), static_cast<const u32x4 *>(src), bytes / 16);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_half_sums(uint32_t *bad, hipStream_t stream) {
+  hipLaunchKernelGGL(probe_half_sums_kernel, dim3(kHalfSumsValues / kBlock), dim3(kBlock), 0, stream, bad);
   return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ STATE_RECORD_BYTES = 32
 EXPORTS = (
     "rfi_params_default", "rfi_plan_create", "rfi_screen", "rfi_destroy", "rfi_last_error",
     "rfi_plan_footprint", "rfi_state_bytes", "rfi_state_get", "rfi_state_set",
-    "rfi_state_reset", "rfi_probe_sink_floats", "rfi_probe_read", "rfi_probe_copy",
+    "rfi_state_reset", "rfi_probe_sink_floats", "rfi_probe_read", "rfi_probe_copy", "rfi_probe_half_sums",
     "rfi_server_create", "rfi_server_now", "rfi_server_submit", "rfi_server_poll",
     "rfi_server_drain", "rfi_server_get_stats", "rfi_server_destroy",
     "rfi_sk_null_moments", "rfi_thresholds_from_pfa", "rfi_calibrate_from_stats",
@@ -138,6 +138,7 @@ def load_library(path: str = LIB_PATH):
         "rfi_probe_sink_floats": (ctypes.c_size_t, [ctypes.c_size_t]),
         "rfi_probe_read": (ctypes.c_int, [vp, ctypes.c_size_t, vp, vp]),
         "rfi_probe_copy": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+        "rfi_probe_half_sums": (ctypes.c_int, [vp, vp]),
         "rfi_server_create": (ctypes.c_int, [P(rfi_server_config), P(vp)]),
         "rfi_server_now": (ctypes.c_double, [vp]),
         "rfi_server_submit": (ctypes.c_int, [vp, P(rfi_request)]),
@@ -263,6 +264,17 @@ def rfi_probe_read(src, nbytes: int, sink, stream=None) -> None:
 
 def rfi_probe_copy(dst, src, nbytes: int, stream=None) -> None:
     _check(load_library().rfi_probe_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)))
+
+
+HALF_SUMS_VALUES = 65536
+
+
+def rfi_probe_half_sums(mismatches, stream=None) -> None:
+    """Device check of the complex-half sums (include/rfi.h); `mismatches` is a device tensor
+    of HALF_SUMS_VALUES 32-bit counters, written by the call."""
+    if hasattr(mismatches, "numel") and mismatches.numel() * mismatches.element_size() < 4 * HALF_SUMS_VALUES:
+        raise ValueError(f"mismatches must hold {HALF_SUMS_VALUES} 32-bit counters")
+    _check(load_library().rfi_probe_half_sums(_ptr(mismatches), _stream_handle(stream)))
 
 
 # --------------------------------------------------------------------------- checked plan wrapper

@@ -88,6 +88,7 @@ def test_null_arguments():
     assert lib.rfi_probe_read(None, 16, None, None) == rfi.RFI_ERR_INVALID_ARGUMENT
     assert lib.rfi_probe_copy(None, None, 16, None) == rfi.RFI_ERR_INVALID_ARGUMENT
     assert lib.rfi_probe_read(32, 17, 64, None) == rfi.RFI_ERR_INVALID_ARGUMENT
+    assert lib.rfi_probe_half_sums(None, None) == rfi.RFI_ERR_INVALID_ARGUMENT
 
 
 def test_unsupported_block_f_reports_unsupported():

@@ -124,6 +124,20 @@ def test_few_long_streams_split_over_waves(fmt, M, T):
         check_cf16(vis, M, f"segmented cf16 M={M} T={T}", **thresholds_for(M))
 
 
+def test_half_sums_are_exact():
+    """The complex-half kernels' sums and differences of binary16 parts (one v_fma_mix_f32
+    each) equal conversion to float32 and a float32 add, bit for bit, for every binary16 value
+    against 1024 others (include/rfi.h, rfi_probe_half_sums)."""
+    import torch
+    from paper_2412_14775_amd import rfi
+    bad = torch.full((rfi.HALF_SUMS_VALUES,), -1, dtype=torch.int32, device="cuda:0")
+    rfi.rfi_probe_half_sums(bad)
+    torch.cuda.synchronize()
+    counts = bad.cpu().numpy()
+    assert counts.min() >= 0, "not every counter was written"
+    assert counts.sum() == 0, f"{int(counts.sum())} differences, first at binary16 0x{int(np.argmax(counts > 0)):04x}"
+
+
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
 @pytest.mark.parametrize("M,T,N", [(300, 3000, 2), (600, 3000, 2), (1000, 3000, 2), (3000, 3000, 2),
                                    (3072, 6144, 2), (768, 6144, 1), (8192, 16384, 1),
