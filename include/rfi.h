@@ -156,7 +156,8 @@ int rfi_plan_footprint(const rfi_plan *plan, size_t *bytes);
  * (statistics in the order tau, r_re, r_im; m2 = sum of squared deviations).
  * rfi_state_get / rfi_state_set copy the whole state to / from host memory
  * synchronously (checkpoint / resume); bytes must equal rfi_state_bytes().
- * rfi_state_reset zeroes it on the given stream.
+ * rfi_state_reset zeroes it on the given stream (one kernel, no memset node, so the
+ * reset may be captured into a graph).
  */
 size_t rfi_state_bytes(const rfi_plan *plan);
 int rfi_state_get(rfi_plan *plan, void *host_dst, size_t bytes);

@@ -3,6 +3,7 @@
 // reporting.  Every argument check runs before any HIP call, so invalid input
 // is rejected without touching a device.
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -127,6 +128,13 @@ int choose_segments(const rfi_params &p, int64_t n_streams) {
          p.n_samples % (2 * n_seg * p.block_m) == 0 && p.n_samples / (2 * n_seg) >= 256)
     n_seg *= 2;
   return n_seg;
+}
+
+// Zeroes n 32-bit words with vector stores.  rfi_state_reset uses this kernel rather than
+// hipMemsetAsync so that a caller may capture the reset in a graph: memset nodes have given
+// wrong results on replays after the first, kernel nodes have not.
+__global__ void __launch_bounds__(256) zero_words(uint32_t *p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0u;
 }
 
 }  // namespace
@@ -302,8 +310,12 @@ int rfi_state_reset(rfi_plan *plan, void *hip_stream) {
   if (plan->state == nullptr) return fail(RFI_ERR_INVALID_ARGUMENT, "plan has no adaptive state");
   DeviceGuard g(plan->device);
   if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
-  hipError_t e = hipMemsetAsync(plan->state, 0, plan->state_bytes, static_cast<hipStream_t>(hip_stream));
-  return e == hipSuccess ? ok() : hip_fail(e, "hipMemsetAsync(state)");
+  const size_t words = plan->state_bytes / 4;
+  const unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 1024);
+  hipLaunchKernelGGL(zero_words, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                     static_cast<uint32_t *>(plan->state), words);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ok() : hip_fail(e, "state reset launch");
 }
 
 size_t rfi_probe_sink_floats(size_t bytes) {

@@ -49,6 +49,43 @@ def test_adaptive_thresholds_follow_oracle_state(fmt, M, F, T, n_warm):
     plan.close()
 
 
+def test_state_reset_replays_in_a_graph():
+    """rfi_state_reset captured in a graph zeroes the state on every replay, with the state
+    rewritten eagerly (rfi_state_set) and a screen run between the replays."""
+    from paper_2412_14775_amd import rfi
+    import torch
+    B, C, T, M = 3, 3, 256, 16                   # two stations: three baselines
+    op, rp = make_params(B, C, T, M, options=oracle.OPT_ADAPTIVE, n_warm=2)
+    plan = rfi.Plan(rp)
+    try:
+        st = plan.state()
+        st["n"] = 7
+        st["mean"] = (1.0, 0.5, 0.25)
+        st["m2"] = (3.0, 2.0, 1.0)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            rfi.rfi_state_reset(plan.handle)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            rfi.rfi_state_reset(plan.handle)
+        vis = to_device(_integration(1, C=C, T=T), "cf32")
+        for rep in range(4):
+            rfi.rfi_state_set(plan.handle, st.view(np.uint8))
+            assert np.array_equal(plan.state().view(np.uint8), st.view(np.uint8))
+            graph.replay()
+            torch.cuda.synchronize()
+            assert not plan.state().view(np.uint8).any(), f"replay {rep}: state not zeroed"
+            run_gpu(plan, vis)                       # eager work between the replays
+            torch.cuda.synchronize()
+            assert plan.state()["n"].sum() > 0
+        del graph
+    finally:
+        plan.close()
+
+
 def test_state_checkpoint_roundtrip_and_reset():
     from paper_2412_14775_amd import rfi
     import torch
