@@ -6,7 +6,7 @@
 //   screen_windows  windows of M = K S samples x F channels (non-power-of-two M and
 //                   the paper's time x frequency windows), optionally in the
 //                   paper's mixed precision (Tables 3-4);
-//   screen_long     time-only windows of at least one step, edges anywhere;
+//   screen_long     time-only windows of more than half a step, edges anywhere;
 //   screen_generic  any other shape, one lane per window.
 //
 // screen_tiled, one pass over the visibilities, bound by HBM bandwidth:
@@ -443,14 +443,15 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
   finish_stream<1>(a, acc, stream, seg, active, wave, lane, xfer);
 }
 
-// Windows of M >= one step of samples (K 64) of one channel, any M: the window
-// edges may fall anywhere inside a step, at most one per step.  Same loads and LDS
-// transpose as the tiled kernel; a step that lies inside the current window, or
-// ends exactly where it does, is summed without per-sample tests.  In a step with
-// an edge inside it the lanes take runs of K + 1 samples that do not cross the
-// edge: the first lanes the samples that close this window, the others those that
-// open the next (66 K / (K+1) lanes at most), so the step costs K + 1 sample slots
-// instead of the 2 K of two masked passes over every lane.  Each lane adds its
+// Windows of more than half a step of samples (K 64 / 2) of one channel, any such M:
+// the window edges may fall anywhere inside a step, at most two per step.  Same loads
+// and LDS transpose as the tiled kernel; a step that lies inside the current window,
+// or ends exactly where it does, is summed without per-sample tests.  In a step with
+// an edge inside it the lanes take runs of K + 1 samples that do not cross an edge:
+// the first lanes the samples that close this window, the next ones a window that
+// lies wholly in the step (when 2 M > K 64 > M), the others those that open the next
+// window (at most 59 lanes), so the step costs K + 1 sample slots instead of the 2 K
+// of two masked passes over every lane.  Each lane adds its
 // step sums plainly for kFold steps before folding them into the window sums, so
 // no lane sums more than kFold K samples in a row whatever M is.
 template <int FMT>
@@ -539,26 +540,41 @@ __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
         for (int j = 0; j < K; ++j) sample(lane * K + j, ps, pr);
         if (n1 == SPI) close_window();
       } else {
-        constexpr int C = K + 1;               // samples per lane in an edge step
-        const int c1 = (n1 + C - 1) / C;       // lanes that take the n1 closing samples
-        const bool closing = lane < c1;
-        const int lo = closing ? lane * C : n1 + (lane - c1) * C;
-        const int hi = min(lo + C, closing ? n1 : SPI);
+        // Pieces of the step: 0, the last n1 samples of window w; 1, all of window w + 1
+        // when it ends in this step too (at most one such window, since 2 M > SPI); 2, the
+        // first samples of the window that goes on into the next step.  Each piece gets
+        // lanes with runs of C samples.
+        constexpr int C = K + 1;
+        const bool whole = n1 + a.M <= SPI;    // uniform
+        const int n2 = whole ? a.M : 0;
+        const int c1 = (n1 + C - 1) / C;       // lanes of piece 0
+        const int c2 = c1 + (n2 + C - 1) / C;  // lanes of pieces 0 and 1
+        const int piece = lane < c1 ? 0 : (lane < c2 ? 1 : 2);
+        const int lo = piece == 0 ? lane * C : (piece == 1 ? n1 + (lane - c1) * C : n1 + n2 + (lane - c2) * C);
+        const int hi = min(lo + C, piece == 0 ? n1 : (piece == 1 ? n1 + n2 : SPI));
         float cs[8] = {}, cr[8] = {};
 #pragma unroll
         for (int j = 0; j < C; ++j)
           if (lo + j < hi) sample(lo + j, cs, cr);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          ps[k] += closing ? cs[k] : 0.0f;
-          pr[k] += closing ? cr[k] : 0.0f;
+          ps[k] += piece == 0 ? cs[k] : 0.0f;
+          pr[k] += piece == 0 ? cr[k] : 0.0f;
         }
         close_window();
-        if (w < a.seg_windows) {               // the other lanes' runs open the next window
+        if (whole) {                           // window w + 1 lies in piece 1
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            ps[k] = closing ? 0.0f : cs[k];
-            pr[k] = closing ? 0.0f : cr[k];
+            ss[k] = piece == 1 ? cs[k] : 0.0f;
+            sr[0][k] = piece == 1 ? cr[k] : 0.0f;
+          }
+          close_window();
+        }
+        if (w < a.seg_windows) {               // piece 2 opens the next window
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            ps[k] = piece == 2 ? cs[k] : 0.0f;
+            pr[k] = piece == 2 ? cr[k] : 0.0f;
           }
         }
       }
@@ -1048,7 +1064,7 @@ KernelKind kernel_for(int M, int F, int fmt, bool mixed) {
   }
   if (F == 1 && tiled_supports(M)) return kTiled;
   if (windows_samples_per_lane(M, F) > 0) return kWindows;
-  if (F == 1 && M >= kWave * (fmt == FMT_CF32 ? 4 : 8)) return kLong;
+  if (F == 1 && 2 * M > kWave * (fmt == FMT_CF32 ? 4 : 8)) return kLong;
   return kGeneric;
 }
 

@@ -141,16 +141,17 @@ def test_half_sums_are_exact():
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
 @pytest.mark.parametrize("M,T,N", [(300, 3000, 2), (600, 3000, 2), (1000, 3000, 2), (3000, 3000, 2),
                                    (3072, 6144, 2), (768, 6144, 1), (8192, 16384, 1),
-                                   (513, 5130, 1), (1023, 8184, 1), (257, 2570, 2), (511, 5110, 1)])
+                                   (513, 5130, 1), (1023, 8184, 1), (257, 2570, 2), (511, 5110, 1),
+                                   (500, 5000, 2), (450, 4050, 1), (131, 1310, 2), (193, 3860, 1)])
 def test_long_windows(fmt, M, T, N):
-    """Windows of at least one step (256 complex64 / 512 complex-half samples) that are not powers
-    of two up to 4096 and have no factor K <= 8 with S <= 64 (the long-window kernel): edges fall
-    anywhere inside a step, steps are ragged at the stream end, and few streams split over waves.
-    A window one sample longer or shorter than a whole number of steps (513, 1023 complex half;
-    257, 511 complex64) walks the edge through every offset of the step, from one sample past its
-    start to one before its end; 3072 and 768 (complex64) end every window with a step.  M = 300
-    (5 x 60) goes to the windowed kernel instead, and 257 and 511 of complex half to the
-    one-lane-per-window kernel (shorter than a step); they stay here as cross-checks."""
+    """Windows of more than half a step (128 complex64 / 256 complex-half samples) that are not
+    powers of two up to 4096 and have no factor K <= 8 with S <= 64 (the long-window kernel):
+    edges fall anywhere inside a step, steps are ragged at the stream end, and few streams split
+    over waves.  A window one sample longer or shorter than a whole number of steps (513, 1023
+    complex half; 257, 511 complex64) walks the edge through every offset of the step; 3072 and
+    768 (complex64) end every window with a step; windows shorter than a step (257-511 complex
+    half, 131 and 193 complex64) put a whole window and two edges into some steps.  M = 300
+    (5 x 60) goes to the windowed kernel instead and stays here as a cross-check."""
     vis = scene_vis(N, 2, T, seed=M + T, duty=(500, 60))
     if fmt == "cf32":
         op, gpu = screen_both(vis, M, **thresholds_for(M))
