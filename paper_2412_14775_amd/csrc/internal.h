@@ -54,8 +54,8 @@ constexpr int kMaxTiledLog2M = 12;  // tiled kernels exist for M = 2 .. 4096
 
 // The kernel that screens windows of M samples x F channels in storage format `fmt`:
 // tiled (F = 1, M a power of two <= 4096), windowed (M = K S, K <= 8, F S <= 64), long
-// (F = 1, M more than half a step: 128 complex64 / 256 complex-half samples), otherwise
-// one lane per window.  The paper's mixed precision exists only in the windowed
+// (F = 1, M more than a quarter of a step: 64 complex64 / 128 complex-half samples),
+// otherwise one lane per window.  The paper's mixed precision exists only in the windowed
 // kernel with complex64 storage (kNone elsewhere).  The tiled and long kernels may split a
 // stream into window-aligned segments (one wave each).
 enum KernelKind { kTiled, kWindows, kLong, kGeneric, kNone };

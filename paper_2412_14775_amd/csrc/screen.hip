@@ -6,7 +6,7 @@
 //   screen_windows  windows of M = K S samples x F channels (non-power-of-two M and
 //                   the paper's time x frequency windows), optionally in the
 //                   paper's mixed precision (Tables 3-4);
-//   screen_long     time-only windows of more than half a step, edges anywhere;
+//   screen_long     time-only windows of more than a quarter of a step, edges anywhere;
 //   screen_generic  any other shape, one lane per window.
 //
 // screen_tiled, one pass over the visibilities, bound by HBM bandwidth:
@@ -443,18 +443,24 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
   finish_stream<1>(a, acc, stream, seg, active, wave, lane, xfer);
 }
 
-// Windows of more than half a step of samples (K 64 / 2) of one channel, any such M:
-// the window edges may fall anywhere inside a step, at most two per step.  Same loads
-// and LDS transpose as the tiled kernel; a step that lies inside the current window,
-// or ends exactly where it does, is summed without per-sample tests.  In a step with
-// an edge inside it the lanes take runs of K + 1 samples that do not cross an edge:
-// the first lanes the samples that close this window, the next ones a window that
-// lies wholly in the step (when 2 M > K 64 > M), the others those that open the next
-// window (at most 59 lanes), so the step costs K + 1 sample slots instead of the 2 K
-// of two masked passes over every lane.  Each lane adds its
+// Windows of more than a quarter of a step of samples (K 64 / 4) of one channel, any
+// such M: the window edges may fall anywhere inside a step, at most four per step.
+// Same loads and LDS transpose as the tiled kernel; a step that lies inside the
+// current window, or ends exactly where it does, is summed without per-sample tests.
+// In a step with an edge inside it the lanes take runs of K + 1 samples that do not
+// cross an edge: the first lanes the samples that close this window, the next ones
+// each window that lies wholly in the step (up to three), the others those that open
+// the next window (at most 62 lanes), so the step costs K + 1 sample slots instead of
+// the 2 K of two masked passes over every lane, plus one wave reduction per window
+// it closes.  Each lane adds its
 // step sums plainly for kFold steps before folding them into the window sums, so
 // no lane sums more than kFold K samples in a row whatever M is.
-template <int FMT>
+constexpr int kLongMaxWhole = 3;  // windows wholly inside one step: M > a quarter of a step
+
+// MAXW: the most windows that lie wholly inside one step for this M (1 when 2 M > a step,
+// else kLongMaxWhole): the edge step is unrolled for that many, and the longer windows
+// keep the shorter code (3 % faster at M = 500-1000, 9 % at complex64 M = 131).
+template <int FMT, int MAXW>
 __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
   constexpr int K = FMT == FMT_CF32 ? 4 : 8;
   constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
@@ -540,18 +546,26 @@ __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
         for (int j = 0; j < K; ++j) sample(lane * K + j, ps, pr);
         if (n1 == SPI) close_window();
       } else {
-        // Pieces of the step: 0, the last n1 samples of window w; 1, all of window w + 1
-        // when it ends in this step too (at most one such window, since 2 M > SPI); 2, the
-        // first samples of the window that goes on into the next step.  Each piece gets
-        // lanes with runs of C samples.
+        // Pieces of the step: 0, the last n1 samples of window w; 1 .. nw, windows that lie
+        // wholly in the step (nw <= MAXW); nw + 1, the first
+        // samples of the window that goes on into the next step.  Each piece gets lanes
+        // with runs of C samples, in order.
         constexpr int C = K + 1;
-        const bool whole = n1 + a.M <= SPI;    // uniform
-        const int n2 = whole ? a.M : 0;
-        const int c1 = (n1 + C - 1) / C;       // lanes of piece 0
-        const int c2 = c1 + (n2 + C - 1) / C;  // lanes of pieces 0 and 1
-        const int piece = lane < c1 ? 0 : (lane < c2 ? 1 : 2);
-        const int lo = piece == 0 ? lane * C : (piece == 1 ? n1 + (lane - c1) * C : n1 + n2 + (lane - c2) * C);
-        const int hi = min(lo + C, piece == 0 ? n1 : (piece == 1 ? n1 + n2 : SPI));
+        const int nw = (SPI - n1) / a.M;       // uniform
+        int piece = -1, lo = SPI, hi = SPI;    // lanes past the last piece take nothing
+        int lanes_before = 0;
+#pragma unroll
+        for (int p = 0; p < MAXW + 2; ++p) {
+          const int start = p == 0 ? 0 : min(n1 + (p - 1) * a.M, SPI);
+          const int end = p == 0 ? n1 : (p <= nw ? n1 + p * a.M : SPI);
+          const int lanes = (end - start + C - 1) / C;
+          if (lane >= lanes_before && lane < lanes_before + lanes) {
+            piece = p;
+            lo = start + (lane - lanes_before) * C;
+            hi = min(lo + C, end);
+          }
+          lanes_before += lanes;
+        }
         float cs[8] = {}, cr[8] = {};
 #pragma unroll
         for (int j = 0; j < C; ++j)
@@ -562,19 +576,22 @@ __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
           pr[k] += piece == 0 ? cr[k] : 0.0f;
         }
         close_window();
-        if (whole) {                           // window w + 1 lies in piece 1
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            ss[k] = piece == 1 ? cs[k] : 0.0f;
-            sr[0][k] = piece == 1 ? cr[k] : 0.0f;
+        for (int p = 1; p <= MAXW; ++p) {
+          if (p <= nw) {                       // window w lies in piece p (uniform)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              ss[k] = piece == p ? cs[k] : 0.0f;
+              sr[0][k] = piece == p ? cr[k] : 0.0f;
+            }
+            close_window();
           }
-          close_window();
         }
-        if (w < a.seg_windows) {               // piece 2 opens the next window
+        if (w < a.seg_windows) {               // piece nw + 1 opens the next window
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            ps[k] = piece == 2 ? cs[k] : 0.0f;
-            pr[k] = piece == 2 ? cr[k] : 0.0f;
+            ps[k] = piece == nw + 1 ? cs[k] : 0.0f;
+            pr[k] = piece == nw + 1 ? cr[k] : 0.0f;
           }
         }
       }
@@ -929,7 +946,10 @@ hipError_t launch_long(const ScreenArgs &a, hipStream_t stream) {
   const int64_t units = a.n_groups * a.n_seg;
   const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
   const unsigned pad = FMT == FMT_CF16 && a.M >= 2048 ? kLongCf16RareEdgePad : 0u;
-  hipLaunchKernelGGL((screen_long<FMT>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
+  if (2 * a.M > kWave * (FMT == FMT_CF32 ? 4 : 8))
+    hipLaunchKernelGGL((screen_long<FMT, 1>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
+  else
+    hipLaunchKernelGGL((screen_long<FMT, kLongMaxWhole>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
   return hipGetLastError();
 }
 
@@ -1064,7 +1084,7 @@ KernelKind kernel_for(int M, int F, int fmt, bool mixed) {
   }
   if (F == 1 && tiled_supports(M)) return kTiled;
   if (windows_samples_per_lane(M, F) > 0) return kWindows;
-  if (F == 1 && 2 * M > kWave * (fmt == FMT_CF32 ? 4 : 8)) return kLong;
+  if (F == 1 && (kLongMaxWhole + 1) * M > kWave * (fmt == FMT_CF32 ? 4 : 8)) return kLong;
   return kGeneric;
 }
 

@@ -43,9 +43,10 @@ static void kernel_choice() {
   EXPECT(kernel_for(300, 1, c32, false) == kWindows && kernel_for(300, 1, c16, false) == kWindows);  // 5 x 60 lanes
   EXPECT(kernel_for(600, 1, c16, false) == kLong && kernel_for(3000, 1, c16, false) == kLong);
   EXPECT(kernel_for(500, 1, c16, false) == kLong && kernel_for(257, 1, c16, false) == kLong);   // > half a step
-  EXPECT(kernel_for(131, 1, c32, false) == kLong && kernel_for(251, 1, c16, false) == kGeneric);
+  EXPECT(kernel_for(131, 1, c32, false) == kLong && kernel_for(131, 1, c16, false) == kLong);   // > a quarter
+  EXPECT(kernel_for(67, 1, c32, false) == kLong && kernel_for(127, 1, c16, false) == kGeneric);
   EXPECT(kernel_for(100, 1, c32, false) == kWindows && kernel_for(15, 2, c16, false) == kWindows);  // 25 of 32, 6 of 8 lanes
-  EXPECT(kernel_for(8192, 2, c32, false) == kGeneric && kernel_for(127, 1, c32, false) == kGeneric);  // no K <= 8 fits
+  EXPECT(kernel_for(8192, 2, c32, false) == kGeneric && kernel_for(61, 1, c32, false) == kGeneric);  // no K <= 8 fits
   EXPECT(windows_samples_per_lane(100, 1) == 4 && windows_samples_per_lane(10, 2) == 5 &&
          windows_samples_per_lane(48, 1) == 6 && windows_samples_per_lane(50, 1) == 2);
   EXPECT(kernel_for(1000, 2, c16, false) == kGeneric);

@@ -142,22 +142,38 @@ def test_half_sums_are_exact():
 @pytest.mark.parametrize("M,T,N", [(300, 3000, 2), (600, 3000, 2), (1000, 3000, 2), (3000, 3000, 2),
                                    (3072, 6144, 2), (768, 6144, 1), (8192, 16384, 1),
                                    (513, 5130, 1), (1023, 8184, 1), (257, 2570, 2), (511, 5110, 1),
-                                   (500, 5000, 2), (450, 4050, 1), (131, 1310, 2), (193, 3860, 1)])
+                                   (500, 5000, 2), (450, 4050, 1), (131, 1310, 2), (193, 3860, 1),
+                                   (251, 2510, 1), (127, 1270, 2), (97, 1940, 1), (67, 1340, 2)])
 def test_long_windows(fmt, M, T, N):
     """Windows of more than half a step (128 complex64 / 256 complex-half samples) that are not
     powers of two up to 4096 and have no factor K <= 8 with S <= 64 (the long-window kernel):
     edges fall anywhere inside a step, steps are ragged at the stream end, and few streams split
     over waves.  A window one sample longer or shorter than a whole number of steps (513, 1023
     complex half; 257, 511 complex64) walks the edge through every offset of the step; 3072 and
-    768 (complex64) end every window with a step; windows shorter than a step (257-511 complex
-    half, 131 and 193 complex64) put a whole window and two edges into some steps.  M = 300
-    (5 x 60) goes to the windowed kernel instead and stays here as a cross-check."""
+    768 (complex64) end every window with a step; windows shorter than a step (131-511 complex
+    half, 67-193 complex64) put up to three whole windows and two edges into a step.  M = 300
+    (5 x 60) goes to the windowed kernel instead, and 67-127 of complex half to the
+    one-lane-per-window kernel; they stay here as cross-checks."""
     vis = scene_vis(N, 2, T, seed=M + T, duty=(500, 60))
     if fmt == "cf32":
         op, gpu = screen_both(vis, M, **thresholds_for(M))
         compare(gpu, vis, op, TOL_F32, label=f"long cf32 M={M} T={T}")
     else:
         check_cf16(vis, M, f"long cf16 M={M} T={T}", **thresholds_for(M))
+
+
+@pytest.mark.parametrize("fmt", ["cf32", "cf16"])
+@pytest.mark.parametrize("M,T", [(61, 1220), (113, 1130)])
+def test_one_lane_per_window_lengths(fmt, M, T):
+    """Prime lengths of at most a quarter of a step (complex64 61; complex half 61 and 113) have
+    no factor K <= 8 with S <= 64: one lane per window, its sums compensated.  Complex64 113 is
+    the long-window kernel's (more than 64 samples)."""
+    vis = scene_vis(2, 3, T, seed=M * 3, duty=(120, 25))
+    if fmt == "cf32":
+        op, gpu = screen_both(vis, M, **thresholds_for(M))
+        compare(gpu, vis, op, TOL_F32, label=f"one lane cf32 M={M}")
+    else:
+        check_cf16(vis, M, f"one lane cf16 M={M}", **thresholds_for(M))
 
 
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
