@@ -454,7 +454,7 @@ def main(argv=None):
                    "block_m": M, "vis_format": "cf32", "seed": SEED},
         "roofline": {"bound": "hbm", "achieved": f32["achieved_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": f32["hbm_frac"], "traffic": traffic,
-                     "kernel": "screen_tiled<0, 6> (complex64, M=64)",
+                     "kernel": "screen_tiled<0, 6, persistent> (complex64, M=64)",
                      "bytes_per_launch": f32["bytes_per_launch"]},
         "cpu_baseline": cpu,
         "latency_ms": {"p50": f32["p50_ms"], "p99": f32["p99_ms"], "deadline": 1000.0},

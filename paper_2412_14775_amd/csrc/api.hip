@@ -27,6 +27,7 @@ struct rfi_plan {
   void *state;  // device, n_streams * 32 bytes, ADAPTIVE only
   size_t state_bytes;
   uint64_t uid;  // rfi::plan_uid
+  int n_cu;      // compute units of `device`
 };
 
 namespace {
@@ -184,6 +185,11 @@ int rfi_plan_create(const rfi_params *params, int device, rfi_plan **out) {
   plan->p = *params;
   plan->uid = g_next_plan_uid.fetch_add(1);
   plan->device = device;
+  e = hipDeviceGetAttribute(&plan->n_cu, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) {
+    delete plan;
+    return hip_fail(e, "hipDeviceGetAttribute(multiprocessor count)");
+  }
   plan->n_streams = (int64_t)params->n_baselines * params->n_channels;
   plan->n_groups = plan->n_streams / params->block_f;
   plan->nW = params->n_samples / params->block_m;
@@ -252,6 +258,7 @@ int rfi_screen(rfi_plan *plan, const void *vis, float *avg, float *weight, uint8
   a.n_warm = p.n_warm;
   a.options = p.options;
   a.invT = (float)(1.0 / (double)p.n_samples);
+  a.n_cu = plan->n_cu;
 
   DeviceGuard g(plan->device);
   if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");

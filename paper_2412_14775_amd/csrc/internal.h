@@ -33,6 +33,7 @@ struct ScreenArgs {
   int32_t n_warm;
   uint32_t options;
   float invT;
+  int32_t n_cu;         // compute units of the device (sizes the persistent tiled launch)
 };
 
 // Adaptive state record, one per stream (32 bytes; layout is part of the ABI).

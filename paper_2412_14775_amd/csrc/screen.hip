@@ -33,6 +33,8 @@
 // No atomics: every reduction has a fixed order, so results are bitwise
 // reproducible run to run.
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace rfi {
@@ -233,7 +235,8 @@ template <int F, bool MIXED = false>
 __device__ __forceinline__ void finish_window(const ScreenArgs &a, const Thresholds &th,
                                               const float tot[8], const float (*wr)[8],
                                               int64_t out_index, bool valid, bool leader,
-                                              StreamAcc<F> &acc) {
+                                              StreamAcc<F> &acc, uint8_t *lds_flags = nullptr,
+                                              int64_t lds_first = 0) {
   float tau, r_re, r_im;
   if constexpr (MIXED) {
     mixed_statistics(a, tot, tau, r_re, r_im);
@@ -261,7 +264,12 @@ __device__ __forceinline__ void finish_window(const ScreenArgs &a, const Thresho
       acc.kept += a.Mt;
       if (a.state != nullptr) moments_push(acc.mom, tau, r_re, r_im);
     }
-    if (a.flags != nullptr) a.flags[out_index] = (uint8_t)bits;
+    if (a.flags != nullptr) {
+      if (lds_flags != nullptr)  // held in LDS (persistent tiled kernel), index from lds_first
+        lds_flags[out_index - lds_first] = (uint8_t)bits;
+      else
+        a.flags[out_index] = (uint8_t)bits;
+    }
     if (a.stats != nullptr) {
       float *s = a.stats + out_index * 3;
       s[0] = tau;
@@ -355,9 +363,13 @@ __device__ __forceinline__ void finish_stream(const ScreenArgs &a, StreamAcc<F> 
   }
 }
 
-// The tiled kernel, for power-of-two window lengths M = 2^LOG2M.
-template <int FMT, int LOG2M>
-__global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
+// The tiled kernel, for power-of-two window lengths M = 2^LOG2M.  One wave per stream
+// segment; or, PERSIST, block b screens the whole streams [b U, (b + 1) U) (wave w every
+// fourth of them from b U + w) and keeps their flags in LDS until the last is done, then
+// writes them in one pass: flag bytes written back to HBM while the reads stream cost
+// many times their size, written after them hardly anything.
+template <int FMT, int LOG2M, bool PERSIST>
+__global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a, int U) {
   constexpr int K = FMT == FMT_CF32 ? 4 : 8;    // samples per lane per step
   constexpr int SB = FMT == FMT_CF32 ? 32 : 16; // bytes per sample
   constexpr int SPI = kWave * K;                // samples per step
@@ -368,13 +380,18 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
 
   __shared__ u32x4 tile[kWavesPerBlock][kTilePieces];
   __shared__ float xfer[kWavesPerBlock][kXfer];
+  extern __shared__ __align__(16) uint8_t block_flags[];  // PERSIST: U nW bytes
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
-  const int64_t unit = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-  const int64_t stream = unit / a.n_seg;
-  const int seg = (int)(unit - stream * a.n_seg);
-  const bool active = stream < a.n_groups;
+  const int64_t first = PERSIST ? (int64_t)blockIdx.x * U : 0;  // the block's streams (PERSIST)
+  const int64_t last = PERSIST ? min(first + (int64_t)U, a.n_groups) : 0;
+  for (int64_t unit = PERSIST ? first + wave : (int64_t)blockIdx.x * kWavesPerBlock + wave;;
+       unit += kWavesPerBlock) {
+  const int64_t stream = PERSIST ? unit : unit / a.n_seg;
+  const int seg = PERSIST ? 0 : (int)(unit - stream * a.n_seg);
+  const bool active = stream < (PERSIST ? last : a.n_groups);
+  if (PERSIST && !active) break;
 
   StreamAcc<1> acc{};
   if (active) {
@@ -421,7 +438,8 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
         if constexpr (LOCAL) {
           if ((j + 1) % M == 0) {
             const int w = (step * SPI + lane * K) / M + j / M;
-            finish_window<1>(a, th, ws, wr, out_base + w, w < a.seg_windows, true, acc);
+            finish_window<1>(a, th, ws, wr, out_base + w, w < a.seg_windows, true, acc,
+                             PERSIST ? block_flags : nullptr, first * a.nW);
 #pragma unroll
             for (int k = 0; k < 8; ++k) ws[k] = wr[0][k] = 0.0f;
           }
@@ -433,7 +451,8 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
 #pragma unroll
           for (int k = 0; k < 8; ++k) tot[k] = group_sum<LPW>(ws[k]);
           const int w = ((step + 1 - IPW) * SPI + lane * K) / M;
-          finish_window<1>(a, th, tot, wr, out_base + w, w < a.seg_windows, lane % LPW == 0, acc);
+          finish_window<1>(a, th, tot, wr, out_base + w, w < a.seg_windows, lane % LPW == 0, acc,
+                           PERSIST ? block_flags : nullptr, first * a.nW);
 #pragma unroll
           for (int k = 0; k < 8; ++k) ws[k] = wr[0][k] = 0.0f;
         }
@@ -441,6 +460,15 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a) {
     }
   }
   finish_stream<1>(a, acc, stream, seg, active, wave, lane, xfer);
+  if (!PERSIST) break;
+  }
+  if constexpr (PERSIST) {
+    __syncthreads();
+    if (a.flags != nullptr) {
+      const int64_t base = first * a.nW, n = (last - first) * a.nW;
+      for (int64_t i = threadIdx.x; i < n; i += kBlock) a.flags[base + i] = block_flags[i];
+    }
+  }
 }
 
 // Windows of more than a quarter of a step of samples (K 64 / 4) of one channel, any
@@ -906,12 +934,32 @@ __global__ void __launch_bounds__(kBlock) screen_generic(const ScreenArgs a) {
 // 12 waves by its registers already.
 constexpr unsigned kCf32OccupancyPad = 7680;
 
+// The persistent complex64 tiled launch: three blocks per CU, each holding at most this many
+// flag bytes in LDS (33 KiB static + 19 KiB < 160 KiB / 3).  Complex64 with flags, one
+// segment per stream: +1 % at M = 64, +4 % at M = 16.  Complex half lost 1-4 % in this form
+// (more registers per loop) and keeps the one-stream-per-wave launch.
+constexpr int kPersistBlocksPerCu = 3;
+constexpr int64_t kPersistFlagBytes = 19456;
+
 template <int FMT, int LOG2M>
 hipError_t launch_tiled(const ScreenArgs &a, hipStream_t stream) {
+  if constexpr (FMT == FMT_CF32) {
+    if (a.n_seg == 1 && a.flags != nullptr && a.n_cu > 0) {
+      const int64_t G = (int64_t)a.n_cu * kPersistBlocksPerCu;
+      const int64_t U = (a.n_groups + G - 1) / G;
+      if (U * a.nW <= kPersistFlagBytes) {
+        const int64_t blocks = (a.n_groups + U - 1) / U;
+        const unsigned lds = (unsigned)std::max<int64_t>(U * a.nW, kCf32OccupancyPad);
+        hipLaunchKernelGGL((screen_tiled<FMT, LOG2M, true>), dim3((unsigned)blocks), dim3(kBlock), lds, stream,
+                           a, (int)U);
+        return hipGetLastError();
+      }
+    }
+  }
   const int64_t units = a.n_groups * a.n_seg;
   const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
   const unsigned pad = FMT == FMT_CF32 ? kCf32OccupancyPad : 0u;
-  hipLaunchKernelGGL((screen_tiled<FMT, LOG2M>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
+  hipLaunchKernelGGL((screen_tiled<FMT, LOG2M, false>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a, 0);
   return hipGetLastError();
 }
 
