@@ -388,79 +388,79 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a, int U
   const int64_t last = PERSIST ? min(first + (int64_t)U, a.n_groups) : 0;
   for (int64_t unit = PERSIST ? first + wave : (int64_t)blockIdx.x * kWavesPerBlock + wave;;
        unit += kWavesPerBlock) {
-  const int64_t stream = PERSIST ? unit : unit / a.n_seg;
-  const int seg = PERSIST ? 0 : (int)(unit - stream * a.n_seg);
-  const bool active = stream < (PERSIST ? last : a.n_groups);
-  if (PERSIST && !active) break;
+    const int64_t stream = PERSIST ? unit : unit / a.n_seg;
+    const int seg = PERSIST ? 0 : (int)(unit - stream * a.n_seg);
+    const bool active = stream < (PERSIST ? last : a.n_groups);
+    if (PERSIST && !active) break;
 
-  StreamAcc<1> acc{};
-  if (active) {
-    const Thresholds th = stream_thresholds(a, stream);
-    const uint8_t *base = a.vis + (stream * a.T + (int64_t)seg * a.seg_samples) * SB;
-    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint8_t *>(base), (short)0, a.seg_samples * SB, kRsrcWord3);
-    const int n_steps = (a.seg_samples + SPI - 1) / SPI;
-    const int64_t out_base = stream * a.nW + (int64_t)seg * a.seg_windows;
-    u32x4 *my_tile = tile[wave];
+    StreamAcc<1> acc{};
+    if (active) {
+      const Thresholds th = stream_thresholds(a, stream);
+      const uint8_t *base = a.vis + (stream * a.T + (int64_t)seg * a.seg_samples) * SB;
+      const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<uint8_t *>(base), (short)0, a.seg_samples * SB, kRsrcWord3);
+      const int n_steps = (a.seg_samples + SPI - 1) / SPI;
+      const int64_t out_base = stream * a.nW + (int64_t)seg * a.seg_windows;
+      u32x4 *my_tile = tile[wave];
 
-    u32x4 buf[kPieces];
-    auto issue = [&](int step) {
+      u32x4 buf[kPieces];
+      auto issue = [&](int step) {
 #pragma unroll
-      for (int i = 0; i < kPieces; ++i)
-        buf[i] = __builtin_bit_cast(
-            u32x4, __builtin_amdgcn_raw_buffer_load_b128(
-                       rsrc, (unsigned)(step * SPI * SB) + (unsigned)((i * kWave + lane) * 16), 0, kLoadStreaming));
-    };
+        for (int i = 0; i < kPieces; ++i)
+          buf[i] = __builtin_bit_cast(
+              u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                         rsrc, (unsigned)(step * SPI * SB) + (unsigned)((i * kWave + lane) * 16), 0, kLoadStreaming));
+      };
 
-    float ws[8] = {}, wr[1][8] = {};
-    issue(0);
-    for (int step = 0; step < n_steps; ++step) {
-      wave_lds_order();
+      float ws[8] = {}, wr[1][8] = {};
+      issue(0);
+      for (int step = 0; step < n_steps; ++step) {
+        wave_lds_order();
 #pragma unroll
-      for (int i = 0; i < kPieces; ++i) my_tile[lds_slot(i * kWave + lane)] = buf[i];
-      wave_lds_order();
-      if (step + 1 < n_steps) issue(step + 1);
+        for (int i = 0; i < kPieces; ++i) my_tile[lds_slot(i * kWave + lane)] = buf[i];
+        wave_lds_order();
+        if (step + 1 < n_steps) issue(step + 1);
 
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
-        float x[8];
-        if constexpr (FMT == FMT_CF32) {
-          const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[lds_slot(kPieces * lane + 2 * j)]);
-          const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[lds_slot(kPieces * lane + 2 * j + 1)]);
-          x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
-          x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
-        } else {
-          const f16x8 h = __builtin_bit_cast(f16x8, my_tile[lds_slot(kPieces * lane + j)]);
+        for (int j = 0; j < K; ++j) {
+          float x[8];
+          if constexpr (FMT == FMT_CF32) {
+            const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[lds_slot(kPieces * lane + 2 * j)]);
+            const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[lds_slot(kPieces * lane + 2 * j + 1)]);
+            x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
+            x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
+          } else {
+            const f16x8 h = __builtin_bit_cast(f16x8, my_tile[lds_slot(kPieces * lane + j)]);
 #pragma unroll
-          for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
+            for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
+          }
+          accumulate_sample(ws, wr[0], x, a.eps);
+          if constexpr (LOCAL) {
+            if ((j + 1) % M == 0) {
+              const int w = (step * SPI + lane * K) / M + j / M;
+              finish_window<1>(a, th, ws, wr, out_base + w, w < a.seg_windows, true, acc,
+                               PERSIST ? block_flags : nullptr, first * a.nW);
+#pragma unroll
+              for (int k = 0; k < 8; ++k) ws[k] = wr[0][k] = 0.0f;
+            }
+          }
         }
-        accumulate_sample(ws, wr[0], x, a.eps);
-        if constexpr (LOCAL) {
-          if ((j + 1) % M == 0) {
-            const int w = (step * SPI + lane * K) / M + j / M;
-            finish_window<1>(a, th, ws, wr, out_base + w, w < a.seg_windows, true, acc,
+        if constexpr (!LOCAL) {
+          if ((step + 1) % IPW == 0) {
+            float tot[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) tot[k] = group_sum<LPW>(ws[k]);
+            const int w = ((step + 1 - IPW) * SPI + lane * K) / M;
+            finish_window<1>(a, th, tot, wr, out_base + w, w < a.seg_windows, lane % LPW == 0, acc,
                              PERSIST ? block_flags : nullptr, first * a.nW);
 #pragma unroll
             for (int k = 0; k < 8; ++k) ws[k] = wr[0][k] = 0.0f;
           }
         }
       }
-      if constexpr (!LOCAL) {
-        if ((step + 1) % IPW == 0) {
-          float tot[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) tot[k] = group_sum<LPW>(ws[k]);
-          const int w = ((step + 1 - IPW) * SPI + lane * K) / M;
-          finish_window<1>(a, th, tot, wr, out_base + w, w < a.seg_windows, lane % LPW == 0, acc,
-                           PERSIST ? block_flags : nullptr, first * a.nW);
-#pragma unroll
-          for (int k = 0; k < 8; ++k) ws[k] = wr[0][k] = 0.0f;
-        }
-      }
     }
-  }
-  finish_stream<1>(a, acc, stream, seg, active, wave, lane, xfer);
-  if (!PERSIST) break;
+    finish_stream<1>(a, acc, stream, seg, active, wave, lane, xfer);
+    if (!PERSIST) break;
   }
   if constexpr (PERSIST) {
     __syncthreads();
