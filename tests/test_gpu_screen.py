@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_helpers import (TOL_F16_TOTAL, TOL_F32, compare, make_params, run_gpu,
+from tests.gpu_helpers import (TOL_F16_TOTAL, TOL_F32, compare, flags_from_stats32, make_params, run_gpu,
                                to_device)
 
 pytestmark = pytest.mark.gpu
@@ -122,6 +122,42 @@ def test_few_long_streams_split_over_waves(fmt, M, T):
         compare(gpu, vis, op, TOL_F32, label=f"segmented cf32 M={M} T={T}")
     else:
         check_cf16(vis, M, f"segmented cf16 M={M} T={T}", **thresholds_for(M))
+
+
+@pytest.mark.parametrize("M", [16, 64])
+def test_persistent_and_per_wave_launches_agree(M):
+    """Complex64 with a flag array and one wave per stream runs the persistent tiled launch (a
+    block's flags held in LDS); without a flag array the same plan runs one wave per stream.
+    48 stations x 32 channels (37 632 streams: no segments) x 256 samples.  Averages, weights and
+    statistics of the two must agree bit for bit, and the persistent launch's flags must be the
+    flag rule applied to those statistics."""
+    import torch
+    from paper_2412_14775_amd import rfi
+    B, C, T = 1176, 32, 256
+    g = torch.Generator(device="cuda:0").manual_seed(M)
+    vis = torch.randn((B, C, T, 4, 2), generator=g, device="cuda:0", dtype=torch.float32)
+    vis[:, 3, 40:48] *= 30.0                                    # some flagged windows
+    th = thresholds_for(M)
+    op = oracle.Params(M=M, **th)
+    rp = rfi.rfi_params_default(n_stations=48, n_baselines=B, n_channels=C, n_samples=T, block_m=M,
+                                vis_format=rfi.RFI_VIS_CF32, sk_d=op.d, sk_low=op.s_low, sk_high=op.s_high,
+                                ds_gamma=op.gamma, eps=op.eps)
+    plan = rfi.Plan(rp)
+    try:
+        with_flags = plan.alloc_outputs(flags=True, stats=True)
+        without = plan.alloc_outputs(flags=False, stats=True)
+        plan.screen(vis, with_flags["avg"], with_flags["weight"], with_flags["flags"], with_flags["stats"])
+        plan.screen(vis, without["avg"], without["weight"], None, without["stats"])
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    for k in ("avg", "weight", "stats"):
+        assert torch.equal(with_flags[k], without[k]), k
+    p32 = op.f32()
+    thb = dict(s_low=p32.s_low, s_high=p32.s_high, gamma=p32.gamma, gamma_im=p32.gamma)
+    flags = with_flags["flags"].cpu().numpy()
+    assert np.array_equal(flags, flags_from_stats32(with_flags["stats"].cpu().numpy(), thb, 0))
+    assert flags.any() and not flags.all()
 
 
 def test_half_sums_are_exact():
