@@ -368,7 +368,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: only --gpus 1 is supported (got {args.gpus}); the screen shards by "
-              "baseline with no exchange, and this build measures one GPU's share.", file=sys.stderr)
+              "baseline with no exchange, and bench.py measures one GPU's share.", file=sys.stderr)
         return 2
 
     scene = synth.scene_fp32_baseline(SEED, N_STATIONS, N_CHANNELS, N_SAMPLES)

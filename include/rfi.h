@@ -43,7 +43,7 @@ typedef enum rfi_status {
   RFI_ERR_INVALID_ARGUMENT = -1, /* bad shape, threshold, pointer or alignment          */
   RFI_ERR_OUT_OF_MEMORY = -2,    /* device allocation failed                             */
   RFI_ERR_DEVICE = -3,           /* a HIP call failed; the message holds HIP's error     */
-  RFI_ERR_UNSUPPORTED = -4       /* valid request this build does not implement          */
+  RFI_ERR_UNSUPPORTED = -4       /* valid request the library does not implement         */
 } rfi_status;
 
 /* Storage format of the visibilities.  Arithmetic is FP32 for both. */
