@@ -486,8 +486,9 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a, int U
 constexpr int kLongMaxWhole = 3;  // windows wholly inside one step: M > a quarter of a step
 
 // MAXW: the most windows that lie wholly inside one step for this M (1 when 2 M > a step,
-// else kLongMaxWhole): the edge step is unrolled for that many, and the longer windows
-// keep the shorter code (3 % faster at M = 500-1000, 9 % at complex64 M = 131).
+// 2 when 3 M > a step, else kLongMaxWhole): the edge step is unrolled for that many, and the
+// longer windows keep the shorter code (MAXW 1 instead of 3: 3 % faster at M = 500-1000, 9 % at
+// complex64 M = 131; MAXW 2 instead of 3: 1-1.5 % at M = 97-251).
 template <int FMT, int MAXW>
 __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
   constexpr int K = FMT == FMT_CF32 ? 4 : 8;
@@ -994,8 +995,11 @@ hipError_t launch_long(const ScreenArgs &a, hipStream_t stream) {
   const int64_t units = a.n_groups * a.n_seg;
   const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
   const unsigned pad = FMT == FMT_CF16 && a.M >= 2048 ? kLongCf16RareEdgePad : 0u;
-  if (2 * a.M > kWave * (FMT == FMT_CF32 ? 4 : 8))
+  const int spi = kWave * (FMT == FMT_CF32 ? 4 : 8);
+  if (2 * a.M > spi)
     hipLaunchKernelGGL((screen_long<FMT, 1>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
+  else if (3 * a.M > spi)
+    hipLaunchKernelGGL((screen_long<FMT, 2>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
   else
     hipLaunchKernelGGL((screen_long<FMT, kLongMaxWhole>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
   return hipGetLastError();
