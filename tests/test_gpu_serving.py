@@ -171,6 +171,46 @@ def test_recreated_plan_gets_its_own_graph():
     assert not np.array_equal(served[0], served[1])
 
 
+def test_persistent_launch_in_served_graphs():
+    """A complex64 array with flags and one wave per stream (32 stations x 64 channels x 256
+    samples: 33 792 streams, no segments) takes the persistent tiled launch, whose flags sit in
+    dynamic LDS: served twice (graph captured, then replayed) it gives the direct screen's
+    results bit for bit."""
+    import torch
+    from paper_2412_14775_amd import rfi
+    N, C, Tl = 32, 64, 256
+    B = N * (N + 1) // 2
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    vis = torch.randn((B, C, Tl, 4, 2), generator=g, device="cuda:0", dtype=torch.float32)
+    vis[:, 7, 64:80] *= 25.0
+    rp = rfi.rfi_params_default(n_stations=N, n_baselines=B, n_channels=C, n_samples=Tl, block_m=16,
+                                vis_format=rfi.RFI_VIS_CF32, sk_d=2.2, sk_low=0.4, sk_high=1.8, ds_gamma=0.45)
+    plan = rfi.Plan(rp)
+    ref = plan.alloc_outputs(flags=True, stats=False)
+    plan.screen(vis, ref["avg"], ref["weight"], ref["flags"], None)
+    torch.cuda.synchronize()
+    want = _host(ref)
+    assert want["flags"].any() and not want["flags"].all()
+    out = plan.alloc_outputs(flags=True, stats=False)
+    srv = rfi.Server(n_slots=2)
+    try:
+        for rep in range(2):
+            for t in out.values():
+                if t is not None:
+                    t.zero_()
+            torch.cuda.synchronize()
+            srv.submit(plan, vis, out, tag=rep)
+            srv.drain(60)
+            assert srv.poll(10)[0]["status"] == 0
+            got = _host(out)
+            for name in ("avg", "weight", "flags"):
+                assert np.array_equal(got[name], want[name], equal_nan=True), (rep, name)
+        assert srv.stats()["graphs"] == 1
+    finally:
+        srv.close()
+        plan.close()
+
+
 def test_admission_respects_the_hbm_budget():
     import torch
     from paper_2412_14775_amd import rfi
