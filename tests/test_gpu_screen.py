@@ -124,13 +124,14 @@ def test_few_long_streams_split_over_waves(fmt, M, T):
         check_cf16(vis, M, f"segmented cf16 M={M} T={T}", **thresholds_for(M))
 
 
-@pytest.mark.parametrize("M", [16, 64])
-def test_persistent_and_per_wave_launches_agree(M):
+@pytest.mark.parametrize("M,adaptive", [(16, False), (64, False), (16, True)])
+def test_persistent_and_per_wave_launches_agree(M, adaptive):
     """Complex64 with a flag array and one wave per stream runs the persistent tiled launch (a
     block's flags held in LDS); without a flag array the same plan runs one wave per stream.
     48 stations x 32 channels (37 632 streams: no segments) x 256 samples.  Averages, weights and
     statistics of the two must agree bit for bit, and the persistent launch's flags must be the
-    flag rule applied to those statistics."""
+    flag rule applied to those statistics; with adaptive thresholds both start from a zeroed
+    state and must leave the same state behind."""
     import torch
     from paper_2412_14775_amd import rfi
     B, C, T = 1176, 32, 256
@@ -141,14 +142,21 @@ def test_persistent_and_per_wave_launches_agree(M):
     op = oracle.Params(M=M, **th)
     rp = rfi.rfi_params_default(n_stations=48, n_baselines=B, n_channels=C, n_samples=T, block_m=M,
                                 vis_format=rfi.RFI_VIS_CF32, sk_d=op.d, sk_low=op.s_low, sk_high=op.s_high,
-                                ds_gamma=op.gamma, eps=op.eps)
+                                ds_gamma=op.gamma, eps=op.eps, options=rfi.RFI_OPT_ADAPTIVE if adaptive else 0)
     plan = rfi.Plan(rp)
     try:
         with_flags = plan.alloc_outputs(flags=True, stats=True)
         without = plan.alloc_outputs(flags=False, stats=True)
         plan.screen(vis, with_flags["avg"], with_flags["weight"], with_flags["flags"], with_flags["stats"])
+        torch.cuda.synchronize()
+        state_after = plan.state().copy() if adaptive else None
+        if adaptive:
+            rfi.rfi_state_reset(plan.handle)
         plan.screen(vis, without["avg"], without["weight"], None, without["stats"])
         torch.cuda.synchronize()
+        if adaptive:
+            assert np.array_equal(plan.state().view(np.uint8), state_after.view(np.uint8))
+            assert state_after["n"].sum() > 0
     finally:
         plan.close()
     for k in ("avg", "weight", "stats"):
