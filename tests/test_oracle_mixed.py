@@ -71,3 +71,23 @@ def test_mixed_flags_agree_with_float64_on_null_data():
     a = oracle.screen(vis, p)
     b = oracle.screen_mixed(vis, p)
     assert (a["flags"] != b["flags"]).mean() < 0.01
+
+
+def test_binary16_unit_vector_sums_by_hand():
+    """Table 4 group 4 sums the unit vectors in 16 bit, sequentially.  Window of W = 16: first
+    (xx, xy, yx, yy) = (1, 0, 0, 0), Re(Q, U, V) = (1, 0, 0); then 15 samples
+    ((1 + 2^-12)/2, s/2, s/2, (1 - 2^-12)/2) with s = +1, -1, ..., +1, i.e. Re(Q, U, V) =
+    (2^-12, s, 0) (float32 exactly; |.| rounds to 1 in float32, p = 1 + eps).  In binary16 each
+    q/p rounds to 2^-12 and 1 + 2^-12 rounds back to 1, so sum q^ = 1; sum u^ = 1 (each u/p rounds
+    to 1); then r_re = sqrt(1^2 + 1^2) / 16 = 1.4140625 / 16 = 0.08837890625 in binary16
+    (sqrt(2) rounds to 1448 / 1024).  Summed in float32 instead, sum q^ = 1.0036621...
+    (1.00390625 in binary16) and r_re = 0.08856201171875; the float64 value is 0.0885503...
+    All parts are real: r_im = 0; |I| = 1 throughout, so tau = 0 exactly."""
+    q = 2.0 ** -12
+    samples = [(1, 0, 0, 0)] + [((1 + q) / 2, s * 0.5, s * 0.5, (1 - q) / 2) for s in [1, -1] * 7 + [1]]
+    win = np.array(samples, np.complex64)[None]
+    tau, r_re, r_im = oracle.mixed_window_stats(win, 1.0, 2.0 ** -23)
+    assert float(r_re[0]) == 0.08837890625
+    assert float(r_im[0]) == 0.0 and float(tau[0]) == 0.0
+    I, Q, U, V = oracle.stokes(win)
+    assert abs(oracle.ds_r(Q.real, U.real, V.real, 2.0 ** -23)[0] - 0.0885503) < 1e-6

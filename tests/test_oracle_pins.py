@@ -271,6 +271,80 @@ def test_worked_window_D_by_hand():
     assert rim[0] == 0.0
 
 
+# Window C: four samples with every correlation nonzero, complex and unequal in size, so that
+# each convention of Section 2 eq. (IQUV) and Section 2.1 shows in the statistics.  The values
+# were computed from the definitions in 50-digit decimal arithmetic (eps = 2^-23, W = 4).
+WIN_C = _w((1 + 2j, 2 - 1j, -1 + 1j, 3), (-2 + 1j, 1j, 2 + 2j, -1 - 1j),
+           (0.5 - 1j, -1 + 0.5j, 1 - 2j, 2 + 1j), (1 + 1j, 3 - 2j, -2, -0.5 + 0.5j))
+C_TAU = {1.0: 0.21878537824648759078730028155504581, 0.5: 0.13127122694789255447238016893302749}
+C_R_RE = 0.51851931750774140389812422056026663
+C_R_IM = 0.20739014015070117673008540179000159
+# the same window under readings the paper does not make (they must not be produced):
+C_WRONG = {
+    "V without j (r_re, r_im)": (0.413889574309308, 0.330967786415696),
+    "SK of |I|^2 (tau, d = 1)": 0.795506044850538,
+    "Table 1 one-line bracket (tau, d = 1)": 0.885452044913154,
+}
+
+
+@pytest.mark.parametrize("d", [1.0, 0.5])
+def test_worked_window_C_high_precision(d):
+    """Window C against its 50-digit values: tau (Section 2.1 eq., Table 1 eps), r_re, r_im
+    (Section 2.2, Table 2 eps), flags SK_LOW | DS_RE at (s_low, s_high, gamma) = (0.5, 2, 0.4)."""
+    tau, rre, rim = _stats(WIN_C, d)
+    assert tau[0] == pytest.approx(C_TAU[d], rel=1e-13)
+    assert rre[0] == pytest.approx(C_R_RE, rel=1e-13)
+    assert rim[0] == pytest.approx(C_R_IM, rel=1e-13)
+    out = oracle.screen(WIN_C[None], Params(M=4, d=d, s_low=0.5, s_high=2.0, gamma=0.4))
+    assert out["flags"].tolist() == [[[SK_LOW | DS_RE]]]
+
+
+def test_worked_window_C_is_not_a_wrong_convention():
+    tau, rre, rim = _stats(WIN_C, 1.0)
+    no_j = C_WRONG["V without j (r_re, r_im)"]
+    assert abs(rre[0] - no_j[0]) > 0.05 and abs(rim[0] - no_j[1]) > 0.05
+    assert abs(tau[0] - C_WRONG["SK of |I|^2 (tau, d = 1)"]) > 0.1
+    assert abs(tau[0] - C_WRONG["Table 1 one-line bracket (tau, d = 1)"]) > 0.1
+    # V = -j (xy - yx) is a reflection of (Q, U, V): the same r
+    I, Q, U, V = oracle.stokes(WIN_C)
+    assert oracle.ds_r(Q.real, U.real, -V.real, EPS)[0] == pytest.approx(C_R_RE, rel=1e-13)
+
+
+def _w20():
+    """A 10 x 2 time x frequency window (W = 20, Sections 3.2 and 4.1), then a second one.
+    Window 0: channel 0 holds 10 x (1, 0, 0, 0) (I = 1, Re(Q, U, V) = (1, 0, 0)); channel 1
+    holds 10 x (1, 1, 1, 1) (I = 2, Re(Q, U, V) = (0, 2, 0)).
+    Window 1, both channels: (1, 0, 0, 0) and (1, 0, 0, 2) alternating (I = 1, 3; Re(Q, U, V) =
+    (1, 0, 0), (-1, 0, 0)), so the directions cancel."""
+    vis = np.zeros((2, 20, 4), complex)
+    vis[0, :10] = (1, 0, 0, 0)
+    vis[1, :10] = (1, 1, 1, 1)
+    vis[:, 10::2] = (1, 0, 0, 0)
+    vis[:, 11::2] = (1, 0, 0, 2)
+    return vis
+
+
+def test_time_frequency_window_W20_by_hand():
+    """W = 20 over two channels.  Window 0: S1 = 10 + 20 = 30, S2 = 10 + 40 = 50, so
+    tau = (20d+1)/19 (20 * 50 / (900 + eps) - 1); the unit vectors sum to (10/(1+eps), 20/(2+eps), 0),
+    r_re = |sum| / 20 (= sqrt(2)/2 at eps = 0), r_im = 0.  Window 1: S1 = 40, S2 = 100,
+    tau = (20d+1)/19 (2000 / (1600 + eps) - 1), r_re = 0.  With d = 3 and (0.5, 2, 0.4), window 0
+    is flagged SK_LOW | DS_RE, window 1 is kept; the flag removes window 0 from both channels'
+    averages, which are then the mean of window 1's samples, (1, 0, 0, 1), with weight 1/2.
+    Had the window been 20 samples of one channel, tau would be 0 - O(eps) and r_re 1 - O(eps)."""
+    d = 3.0
+    out = oracle.screen(_w20()[None], Params(M=10, F=2, d=d, s_low=0.5, s_high=2.0, gamma=0.4))
+    pre = (20 * d + 1) / 19
+    assert out["tau"][0, 0, 0] == pytest.approx(pre * (1000 / (900 + EPS) - 1), rel=1e-13)
+    assert out["tau"][0, 0, 1] == pytest.approx(pre * (2000 / (1600 + EPS) - 1), rel=1e-13)
+    r0 = math.hypot(10 / (1 + EPS), 20 / (2 + EPS)) / 20
+    assert out["r_re"][0, 0, 0] == pytest.approx(r0, rel=1e-14)
+    assert out["r_re"][0, 0, 1] == 0.0 and np.all(out["r_im"] == 0.0)
+    assert out["flags"].tolist() == [[[SK_LOW | DS_RE, 0]]]
+    np.testing.assert_array_equal(out["avg"][0], [[1, 0, 0, 1], [1, 0, 0, 1]])
+    np.testing.assert_array_equal(out["weight"][0], [0.5, 0.5])
+
+
 def test_masked_average_worked_example():
     """T = 8, M = 4, windows [D, B], (s_low, s_high, gamma) = (0.5, 2, 0.4), d = 1:
     D: tau = 5/3, r_re = 0.354, r_im = 0 -> kept;  B: tau = 5 > 2 -> SK_HIGH.
