@@ -151,9 +151,12 @@ const char *rfi_last_error(void);
 int rfi_plan_footprint(const rfi_plan *plan, size_t *bytes);
 
 /*
- * ADAPTIVE state, per channel group b*(C/F) + c/F (per stream when F = 1), 32 bytes:
- *   uint32 n; float mean[3]; float m2[3]; uint32 reserved
- * (statistics in the order tau, r_re, r_im; m2 = sum of squared deviations).
+ * ADAPTIVE state, per channel group b*(C/F) + c/F (per stream when F = 1), 64 bytes:
+ *   uint64 n; double mean[3]; double m2[3]; uint64 reserved
+ * (statistics in the order tau, r_re, r_im; n = clean windows so far, exact; m2 = sum of
+ * squared deviations).  Each call merges its integration's moments into it in float64
+ * (Chan, Golub & LeVeque 1979): a float32 state would drift from the exact running values
+ * by more than 1e-5 relative within 1e4-1e5 integrations.
  * rfi_state_get / rfi_state_set copy the whole state to / from host memory
  * synchronously (checkpoint / resume); bytes must equal rfi_state_bytes().
  * rfi_state_reset zeroes it on the given stream (one kernel, no memset node, so the
@@ -224,7 +227,8 @@ int rfi_calibrate_from_stats(const float *stats, size_t n_windows, int32_t W, fl
  * and that integration's device buffers, plus an arrival time on the server clock.  A
  * scheduler thread releases requests at their arrival time into a FIFO queue and admits
  * a request when (a) a slot (one HIP stream each) is free, (b) the footprint of all
- * admitted requests plus this one's (rfi_plan_footprint) stays within the HBM budget, and
+ * admitted requests plus this one's (rfi_plan_footprint, plus the statistics output
+ * [B][C/F][T/M][3] float32 when the request writes it) stays within the HBM budget, and
  * (c) no earlier request of the same plan is still queued or running (per-plan order keeps
  * the adaptive state update sequence of that array).  A request that cannot be admitted
  * does not block later requests of other plans.  Each admitted request replays a hipGraph
@@ -232,7 +236,10 @@ int rfi_calibrate_from_stats(const float *stats, size_t n_windows, int32_t W, fl
  * stream; a host callback timestamps completion.  Requests of different arrays therefore
  * overlap on the device, and each result is bitwise the same as when run alone.  Graphs
  * are cached per plan identity, not per plan address: a plan created after another was
- * destroyed never replays the old plan's graph, even at the same address.  A failed
+ * destroyed never replays the old plan's graph, even at the same address.  The cache holds
+ * at most max_graphs graphs; when it is full the least recently used graph that no request
+ * on the device replays is freed (graphs of destroyed plans and of buffer sets no longer
+ * used age out this way), so a long run with fresh buffers stays bounded.  A failed
  * request completes with its status in rfi_completion.status; its message is recorded on
  * the scheduler thread, so rfi_last_error on the caller's thread does not show it.
  * ------------------------------------------------------------------------------------------ */
@@ -243,6 +250,8 @@ typedef struct rfi_server_config {
   int32_t n_slots;         /* requests on the device at once (HIP streams), 1..64               */
   uint64_t hbm_budget;     /* bytes: cap on the summed footprint of admitted requests, > 0      */
   int32_t use_graphs;      /* 1: replay captured hipGraphs; 0: launch rfi_screen directly       */
+  int32_t max_graphs;      /* graphs kept cached at most (0: 256); the least recently used one
+                              that no request on the device replays is freed first               */
 } rfi_server_config;
 
 typedef struct rfi_request {
@@ -270,6 +279,8 @@ typedef struct rfi_server_stats {
   uint64_t peak_inflight_bytes;  /* largest summed footprint of admitted requests                */
   int32_t peak_inflight;         /* largest number of requests on the device at once            */
   int32_t graphs;                /* graphs captured so far                                      */
+  int32_t graphs_cached;         /* graphs held in the cache now (<= max_graphs unless every
+                                    cached graph was on the device when a new one was needed) */
 } rfi_server_stats;
 
 /* Create the server and start its scheduler thread.  Errors: INVALID_ARGUMENT, DEVICE. */
@@ -277,7 +288,8 @@ int rfi_server_create(const rfi_server_config *cfg, rfi_server **out);
 /* Seconds since the server was created (monotonic clock). */
 double rfi_server_now(const rfi_server *srv);
 /* Queue a request (thread-safe; returns at once).  INVALID_ARGUMENT if a pointer is NULL or
- * the plan's footprint alone exceeds the budget (the request could never be admitted).
+ * the request's footprint alone exceeds the budget (the request could never be admitted).
+ * The plan must stay alive (not rfi_destroy'ed) until the request's completion is polled.
  * The server's streams wait on no other stream: the input must be complete in device memory
  * when the request is submitted (synchronize the stream that produced it first), and the
  * buffers must stay untouched until the request's completion has been polled. */

@@ -24,7 +24,7 @@ struct rfi_plan {
   int32_t nW;
   int32_t n_seg;
   size_t sample_bytes;
-  void *state;  // device, n_streams * 32 bytes, ADAPTIVE only
+  void *state;  // device, n_groups * sizeof(rfi::StateRec) bytes, ADAPTIVE only
   size_t state_bytes;
   uint64_t uid;  // rfi::plan_uid
   int n_cu;      // compute units of `device`
@@ -142,6 +142,8 @@ __global__ void __launch_bounds__(256) zero_words(uint32_t *p, size_t n) {
 
 uint64_t rfi::plan_uid(const rfi_plan *plan) { return plan->uid; }
 
+size_t rfi::plan_stats_bytes(const rfi_plan *plan) { return (size_t)plan->n_groups * plan->nW * 3 * sizeof(float); }
+
 int rfi::set_error(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
@@ -235,7 +237,7 @@ int rfi_screen(rfi_plan *plan, const void *vis, float *avg, float *weight, uint8
   a.weight = weight;
   a.flags = flags;
   a.stats = stats;
-  a.state = static_cast<uint32_t *>(plan->state);
+  a.state = static_cast<rfi::StateRec *>(plan->state);
   a.n_groups = plan->n_groups;
   a.F = p.block_f;
   a.T = p.n_samples;

@@ -7,6 +7,19 @@
 
 namespace rfi {
 
+// Adaptive state record, one per channel group (64 bytes; layout is part of the ABI): the
+// exact count of clean windows and the float64 running mean and sum of squared deviations
+// of (tau, r_re, r_im).  A float32 state drifts from the float64 one by about 1e-5 (mean)
+// and 1e-4 (M2) relative after 1e5 integrations of 48 windows, which the 1e-5 tolerance
+// does not allow; each integration's own moments stay float32 (at most T / 2 windows).
+struct StateRec {
+  uint64_t n;
+  double mean[3];
+  double m2[3];
+  uint64_t reserved;
+};
+static_assert(sizeof(StateRec) == 64, "state record is 64 bytes");
+
 // Launch arguments of the screen kernels (passed by value as the kernel argument).
 struct ScreenArgs {
   const uint8_t *vis;   // [streams][T] samples of `sample_bytes` each
@@ -14,7 +27,7 @@ struct ScreenArgs {
   float *weight;        // [streams]
   uint8_t *flags;       // [streams][nW] or null
   float *stats;         // [streams][nW][3] or null
-  uint32_t *state;      // [groups][8] adaptive state or null
+  StateRec *state;      // [groups] adaptive state or null
   int64_t n_groups;     // B * C / F: channel groups (= streams when F = 1)
   int32_t F;            // channels per window (1, 2 or 4)
   int32_t T;            // samples per stream
@@ -36,14 +49,6 @@ struct ScreenArgs {
   int32_t n_cu;         // compute units of the device (sizes the persistent tiled launch)
 };
 
-// Adaptive state record, one per stream (32 bytes; layout is part of the ABI).
-struct StateRec {
-  uint32_t n;
-  float mean[3];
-  float m2[3];
-  uint32_t reserved;
-};
-static_assert(sizeof(StateRec) == 32, "state record is 32 bytes");
 
 enum : int { FMT_CF32 = 0, FMT_CF16 = 1 };
 constexpr uint32_t kOptPaperMixed = 8u;  // RFI_OPT_PAPER_MIXED

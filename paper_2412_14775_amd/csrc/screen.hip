@@ -80,16 +80,17 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
-// Running (count, mean, sum of squared deviations) of the three statistics.
+// Running (count, mean, sum of squared deviations) of the three statistics over one
+// integration's clean windows (float32 sums; the count is exact).
 struct Moments {
-  float n;
+  uint32_t n;
   float m[3];
   float s[3];
 };
 
 __device__ __forceinline__ void moments_push(Moments &a, float x0, float x1, float x2) {
-  a.n += 1.0f;
-  const float inv = 1.0f / a.n;
+  a.n += 1u;
+  const float inv = 1.0f / (float)a.n;
   const float x[3] = {x0, x1, x2};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -101,10 +102,10 @@ __device__ __forceinline__ void moments_push(Moments &a, float x0, float x1, flo
 
 // Pairwise merge of Chan, Golub & LeVeque (1979).
 __device__ __forceinline__ Moments moments_merge(const Moments &a, const Moments &b) {
-  const float n = a.n + b.n;
-  if (n == 0.0f) return a;
-  const float fb = b.n / n;
-  const float cross = a.n * b.n / n;
+  const uint32_t n = a.n + b.n;
+  if (n == 0u) return a;
+  const float fb = (float)b.n / (float)n;
+  const float cross = (float)a.n * fb;
   Moments r;
   r.n = n;
 #pragma unroll
@@ -118,7 +119,7 @@ __device__ __forceinline__ Moments moments_merge(const Moments &a, const Moments
 
 __device__ __forceinline__ Moments moments_shfl_xor(const Moments &a, int mask) {
   Moments b;
-  b.n = __shfl_xor(a.n, mask);
+  b.n = (uint32_t)__shfl_xor((int)a.n, mask);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     b.m[k] = __shfl_xor(a.m[k], mask);
@@ -135,21 +136,38 @@ struct Thresholds {
 __device__ __forceinline__ Thresholds stream_thresholds(const ScreenArgs &a, int64_t stream) {
   Thresholds t{a.s_low, a.s_high, a.gamma, a.gamma};
   if (a.state != nullptr) {
-    const StateRec *st = reinterpret_cast<const StateRec *>(a.state) + stream;
-    const uint32_t n = st->n;
-    const uint32_t warm = a.n_warm > 2 ? (uint32_t)a.n_warm : 2u;
-    if (n >= warm) {
-      const float inv = 1.0f / (float)(n - 1);
-      const float sd0 = sqrtf(st->m2[0] * inv);
-      const float sd1 = sqrtf(st->m2[1] * inv);
-      const float sd2 = sqrtf(st->m2[2] * inv);
-      t.s_low = st->mean[0] - a.kappa_sk * sd0;
-      t.s_high = st->mean[0] + a.kappa_sk * sd0;
-      t.g_re = st->mean[1] + a.kappa_ds * sd1;
-      t.g_im = st->mean[2] + a.kappa_ds * sd2;
+    const StateRec &st = a.state[stream];
+    const uint64_t n = st.n;
+    const uint64_t warm = a.n_warm > 2 ? (uint64_t)a.n_warm : 2u;
+    if (n >= warm) {  // float64 like the state; the comparisons are float32
+      const double inv = 1.0 / (double)(n - 1);
+      const double sd0 = sqrt(st.m2[0] * inv);
+      const double sd1 = sqrt(st.m2[1] * inv);
+      const double sd2 = sqrt(st.m2[2] * inv);
+      t.s_low = (float)(st.mean[0] - (double)a.kappa_sk * sd0);
+      t.s_high = (float)(st.mean[0] + (double)a.kappa_sk * sd0);
+      t.g_re = (float)(st.mean[1] + (double)a.kappa_ds * sd1);
+      t.g_im = (float)(st.mean[2] + (double)a.kappa_ds * sd2);
     }
   }
   return t;
+}
+
+// The integration's moments b merged into the stream's state (Chan, Golub & LeVeque), in
+// float64 with the exact count: n' = n + n_b, mean' = mean + delta n_b / n',
+// M2' = M2 + M2_b + delta^2 n n_b / n'.
+__device__ __forceinline__ void state_merge(StateRec *st, const Moments &b) {
+  StateRec r = *st;
+  const double fb = (double)b.n / (double)(r.n + b.n);
+  const double cross = (double)r.n * fb;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double d = (double)b.m[k] - r.mean[k];
+    r.mean[k] += d * fb;
+    r.m2[k] += (double)b.s[k] + d * d * cross;
+  }
+  r.n += b.n;
+  *st = r;
 }
 
 // Per-sample terms of Tables 1 and 2 from one sample's Stokes parameters (eq. IQUV),
@@ -305,7 +323,7 @@ __device__ __forceinline__ void finish_stream(const ScreenArgs &a, StreamAcc<F> 
 #pragma unroll
         for (int k = 0; k < 8; ++k) xfer[wave][8 * f + k] = acc.sum[f][k];
       xfer[wave][o] = acc.kept;
-      xfer[wave][o + 1] = acc.mom.n;
+      xfer[wave][o + 1] = __uint_as_float(acc.mom.n);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         xfer[wave][o + 2 + k] = acc.mom.m[k];
@@ -322,7 +340,7 @@ __device__ __forceinline__ void finish_stream(const ScreenArgs &a, StreamAcc<F> 
           for (int k = 0; k < 8; ++k) acc.sum[f][k] += x[8 * f + k];
         acc.kept += x[o];
         Moments b;
-        b.n = x[o + 1];
+        b.n = __float_as_uint(x[o + 1]);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           b.m[k] = x[o + 2 + k];
@@ -342,25 +360,7 @@ __device__ __forceinline__ void finish_stream(const ScreenArgs &a, StreamAcc<F> 
     out[1] = f32x4{acc.sum[f][4] * inv, acc.sum[f][5] * inv, acc.sum[f][6] * inv, acc.sum[f][7] * inv};
     a.weight[stream] = acc.kept * a.invT;
   }
-  if (a.state != nullptr && acc.mom.n > 0.0f) {
-    StateRec *st = reinterpret_cast<StateRec *>(a.state) + group;
-    StateRec r = *st;
-    Moments old;
-    old.n = (float)r.n;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      old.m[k] = r.mean[k];
-      old.s[k] = r.m2[k];
-    }
-    const Moments nw = moments_merge(old, acc.mom);
-    r.n += (uint32_t)acc.mom.n;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      r.mean[k] = nw.m[k];
-      r.m2[k] = nw.s[k];
-    }
-    *st = r;
-  }
+  if (a.state != nullptr && acc.mom.n > 0u) state_merge(a.state + group, acc.mom);
 }
 
 // The tiled kernel, for power-of-two window lengths M = 2^LOG2M.  One wave per stream
@@ -423,18 +423,14 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a, int U
 
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-          float x[8];
           if constexpr (FMT == FMT_CF32) {
             const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[lds_slot(kPieces * lane + 2 * j)]);
             const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[lds_slot(kPieces * lane + 2 * j + 1)]);
-            x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
-            x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
+            const float x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            accumulate_sample(ws, wr[0], x, a.eps);
           } else {
-            const f16x8 h = __builtin_bit_cast(f16x8, my_tile[lds_slot(kPieces * lane + j)]);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
+            accumulate_sample_h(ws, wr[0], my_tile[lds_slot(kPieces * lane + j)], a.eps);
           }
-          accumulate_sample(ws, wr[0], x, a.eps);
           if constexpr (LOCAL) {
             if ((j + 1) % M == 0) {
               const int w = (step * SPI + lane * K) / M + j / M;
@@ -659,15 +655,29 @@ __device__ __forceinline__ void accumulate_sample_mixed(float ws[8], float wr[8]
   for (int k = 0; k < 8; ++k) wr[k] += x[k];
 }
 
-// Group sum whose additions round to binary16 (operands are binary16 values).
-__device__ __forceinline__ float group_sum16_rt(float v, int L) {
-  if (L >= 2) v = round16(v + dpp_mov<0xB1>(v));
-  if (L >= 4) v = round16(v + dpp_mov<0x4E>(v));
-  if (L >= 8) v = round16(v + dpp_mov<0x141>(v));
-  if (L >= 16) v = round16(v + dpp_mov<0x140>(v));
-  if (L >= 32) v = round16(v + __shfl_xor(v, 16));
-  if (L >= 64) v = round16(v + __shfl_xor(v, 32));
-  return v;
+// One butterfly level of the window sums v[0..7] over aligned groups of lanes (the partner
+// of each lane by the DPP control CTRL, or lane ^ XOR when CTRL is 0).  Sums R16 .. 7 round
+// each addition to binary16 (the paper's mixed precision: R16 = 2, else 8 for none).
+template <int CTRL, int XOR, int R16>
+__device__ __forceinline__ void group_level8(float v[8]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float o = CTRL != 0 ? dpp_mov<CTRL>(v[e]) : __shfl_xor(v[e], XOR);
+    v[e] = e >= R16 ? round16(v[e] + o) : v[e] + o;
+  }
+}
+
+// The eight window sums over aligned groups of L lanes, L a run-time power of two (uniform):
+// one branch per level rather than per sum and level.  Every lane of a group receives the
+// same totals, as group_sum gives them.
+template <int R16>
+__device__ __forceinline__ void group_sum8_rt(float v[8], int L) {
+  if (L >= 2) group_level8<0xB1, 0, R16>(v);
+  if (L >= 4) group_level8<0x4E, 0, R16>(v);
+  if (L >= 8) group_level8<0x141, 0, R16>(v);
+  if (L >= 16) group_level8<0x140, 0, R16>(v);
+  if (L >= 32) group_level8<0, 16, R16>(v);
+  if (L >= 64) group_level8<0, 32, R16>(v);
 }
 
 // tau, r_re, r_im from window totals in the mixed precision.
@@ -685,17 +695,6 @@ __device__ __forceinline__ void mixed_statistics(const ScreenArgs &a, const floa
   };
   r_re = r16(tot[2], tot[3], tot[4]);
   r_im = r16(tot[5], tot[6], tot[7]);
-}
-
-// Sum over aligned groups of L lanes for a run-time power of two L (uniform branches).
-__device__ __forceinline__ float group_sum_rt(float v, int L) {
-  if (L >= 2) v += dpp_mov<0xB1>(v);
-  if (L >= 4) v += dpp_mov<0x4E>(v);
-  if (L >= 8) v += dpp_mov<0x141>(v);
-  if (L >= 16) v += dpp_mov<0x140>(v);
-  if (L >= 32) v += __shfl_xor(v, 16);
-  if (L >= 64) v += __shfl_xor(v, 32);
-  return v;
 }
 
 // Windows of M = K S time samples x F channels, K <= 8, F S <= 64 lanes per
@@ -732,9 +731,7 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
   const int ch_samples = GEN ? wps * a.M : CH_SAMPLES;
   const int ch_pieces = ch_samples * PPS;
 
-  float acc[8] = {};
-  float kept = 0.0f;
-  Moments mom{};
+  StreamAcc<1> acc{};                           // this lane's channel: masked sums, kept, moments
   if (active) {
     const Thresholds th = stream_thresholds(a, group);
     const uint8_t *base = a.vis + group * F * (int64_t)a.T * SB;
@@ -782,25 +779,18 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
           accumulate_sample_h(ws, wr, my_tile[my_piece + k], a.eps);
         }
       }
-      float tot[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) tot[e] = (MIXED && e >= 2) ? group_sum16_rt(ws[e], L) : group_sum_rt(ws[e], L);
+      group_sum8_rt<MIXED ? 2 : 8>(ws, L);     // ws now holds the window totals
       const int w = step * wps + j;
       const bool valid = w < a.nW;
-      // one lane per window plays the leader of finish_window; every lane folds
-      // its own raw partial into its own channel's sum
-      StreamAcc<1> one{};
+      // one lane per window plays the leader of finish_window (kept count, moments, flag and
+      // statistics); every lane folds its own raw partial into its own channel's sum
       const float wr1[1][8] = {{wr[0], wr[1], wr[2], wr[3], wr[4], wr[5], wr[6], wr[7]}};
       if constexpr (MIXED) {
         Thresholds t16{round16(th.s_low), round16(th.s_high), round16(th.g_re), round16(th.g_im)};
-        finish_window<1, true>(a, t16, tot, wr1, group * a.nW + w, valid, g == 0, one);
+        finish_window<1, true>(a, t16, ws, wr1, group * a.nW + w, valid, g == 0, acc);
       } else {
-        finish_window<1>(a, th, tot, wr1, group * a.nW + w, valid, g == 0, one);
+        finish_window<1>(a, th, ws, wr1, group * a.nW + w, valid, g == 0, acc);
       }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) acc[e] += one.sum[0][e];
-      kept += one.kept;
-      if (a.state != nullptr && one.mom.n > 0.0f) mom = moments_merge(mom, one.mom);
     }
   }
   // masked sums: reduce over the lanes of each channel
@@ -809,17 +799,18 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
 #pragma unroll
     for (int c = 0; c < F; ++c)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) chan[c][e] = group_sum<64>(act && f == c ? acc[e] : 0.0f);
+      for (int e = 0; e < 8; ++e) chan[c][e] = group_sum<64>(act && f == c ? acc.sum[0][e] : 0.0f);
   } else {                                      // skip the f bits of the lane index
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      float v = acc[e];
+      float v = acc.sum[0][e];
       for (int m = 1; m < kWave; m <<= 1)
         if (m < S || m >= L) v += __shfl_xor(v, m);
       chan[0][e] = v;
     }
   }
-  kept = group_sum<64>(kept);
+  const float kept = group_sum<64>(acc.kept);
+  Moments mom = acc.mom;
   if (a.state != nullptr) {
 #pragma unroll
     for (int m = 1; m < kWave; m <<= 1) mom = moments_merge(mom, moments_shfl_xor(mom, m));
@@ -840,25 +831,7 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
   } else if (lane < L && s == 0) {              // lane f S of window 0 writes channel f
     write_channel(f, chan[0]);
   }
-  if (lane == 0 && a.state != nullptr && mom.n > 0.0f) {
-    StateRec *st = reinterpret_cast<StateRec *>(a.state) + group;
-    StateRec r = *st;
-    Moments old;
-    old.n = (float)r.n;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      old.m[k] = r.mean[k];
-      old.s[k] = r.m2[k];
-    }
-    const Moments nw = moments_merge(old, mom);
-    r.n += (uint32_t)mom.n;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      r.mean[k] = nw.m[k];
-      r.m2[k] = nw.s[k];
-    }
-    *st = r;
-  }
+  if (lane == 0 && a.state != nullptr && mom.n > 0u) state_merge(a.state + group, mom);
 }
 
 // s += b with the running compensation c (Kahan): the error of a long sum of

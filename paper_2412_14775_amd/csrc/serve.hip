@@ -42,6 +42,18 @@ struct GraphKey {
   }
 };
 
+struct CachedGraph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  uint64_t last_use;  // scheduler's use counter at the last replay
+};
+
+constexpr int32_t kDefaultMaxGraphs = 256;
+
+GraphKey key_of(const rfi_request &r) {
+  return GraphKey{rfi::plan_uid(r.plan), r.vis, r.avg, r.weight, r.flags, r.stats};
+}
+
 struct Pending {
   rfi_request req;
   uint64_t bytes;
@@ -70,9 +82,16 @@ struct rfi_server {
   std::vector<const rfi_plan *> slot_plan;
   std::vector<uint64_t> slot_bytes;
   std::vector<rfi_completion> slot_rec;
+  std::vector<GraphKey> slot_key;          // graph key of each busy slot's request
   std::vector<SlotCtx> ctx;
   std::deque<rfi_completion> done;
-  std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  // Captured graphs, touched by the scheduler thread only (and by rfi_server_destroy after
+  // it has joined): at most max_graphs of them, the least recently used not on the device
+  // freed first, so a long run with fresh buffers or short-lived plans stays bounded.
+  std::map<GraphKey, CachedGraph> graphs;
+  int32_t max_graphs = kDefaultMaxGraphs;
+  uint64_t use_clock = 0;
+  std::atomic<int> n_cached{0};
   uint64_t inflight_bytes = 0;
   int inflight = 0;
   uint64_t outstanding = 0;
@@ -113,9 +132,28 @@ void rfi_server::on_done(void *p) {
 int rfi_server::launch(int slot, const rfi_request &r) {
   hipStream_t st = streams[slot];
   if (!cfg.use_graphs) return rfi_screen(r.plan, r.vis, r.avg, r.weight, r.flags, r.stats, st);
-  const GraphKey key{rfi::plan_uid(r.plan), r.vis, r.avg, r.weight, r.flags, r.stats};
+  const GraphKey key = key_of(r);
   auto it = graphs.find(key);
   if (it == graphs.end()) {
+    if ((int64_t)graphs.size() >= max_graphs) {
+      // pick the victim under the mutex (slot_busy / slot_key), free it without: a slot that
+      // is not busy has run its completion callback, which follows its graph on the stream
+      auto victim = graphs.cend();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        auto in_use = [this](const GraphKey &k) {
+          for (int s = 0; s < cfg.n_slots; ++s)
+            if (slot_busy[s] && !(slot_key[s] < k) && !(k < slot_key[s])) return true;
+          return false;
+        };
+        victim = rfi::graph_to_evict(graphs, key, in_use);
+      }
+      if (victim != graphs.cend()) {
+        (void)hipGraphExecDestroy(victim->second.exec);
+        (void)hipGraphDestroy(victim->second.graph);
+        graphs.erase(victim);
+      }
+    }
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -130,10 +168,12 @@ int rfi_server::launch(int slot, const rfi_request &r) {
       (void)hipGraphDestroy(g);
       return set_error(RFI_ERR_DEVICE, "hipGraphInstantiate failed");
     }
-    it = graphs.emplace(key, std::make_pair(g, ge)).first;
+    it = graphs.emplace(key, CachedGraph{g, ge, 0}).first;
     n_graphs.fetch_add(1);
   }
-  if (hipGraphLaunch(it->second.second, st) != hipSuccess) return set_error(RFI_ERR_DEVICE, "hipGraphLaunch failed");
+  it->second.last_use = ++use_clock;
+  n_cached.store((int)graphs.size());
+  if (hipGraphLaunch(it->second.exec, st) != hipSuccess) return set_error(RFI_ERR_DEVICE, "hipGraphLaunch failed");
   return RFI_OK;
 }
 
@@ -171,6 +211,7 @@ void rfi_server::run() {
       queue.erase(queue.begin() + k);  // only this thread touches `queue`
       slot_busy[slot] = true;
       slot_plan[slot] = plan;
+      slot_key[slot] = key_of(p.req);
       slot_bytes[slot] = p.bytes;
       inflight_bytes += p.bytes;
       inflight += 1;
@@ -226,12 +267,14 @@ int rfi_server_create(const rfi_server_config *cfg, rfi_server **out) {
   if (cfg->n_slots < 1 || cfg->n_slots > 64) return set_error(RFI_ERR_INVALID_ARGUMENT, "n_slots must be in 1..64");
   if (cfg->hbm_budget == 0) return set_error(RFI_ERR_INVALID_ARGUMENT, "hbm_budget must be > 0");
   if (cfg->device < 0) return set_error(RFI_ERR_INVALID_ARGUMENT, "device must be >= 0");
+  if (cfg->max_graphs < 0) return set_error(RFI_ERR_INVALID_ARGUMENT, "max_graphs must be >= 0 (0: the default)");
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || cfg->device >= count)
     return set_error(RFI_ERR_DEVICE, "device not available");
   rfi_server *s = new (std::nothrow) rfi_server();
   if (s == nullptr) return set_error(RFI_ERR_OUT_OF_MEMORY, "host allocation failed");
   s->cfg = *cfg;
+  s->max_graphs = cfg->max_graphs > 0 ? cfg->max_graphs : kDefaultMaxGraphs;
   s->t0 = Clock::now();
   int prev = 0;
   (void)hipGetDevice(&prev);
@@ -242,6 +285,7 @@ int rfi_server_create(const rfi_server_config *cfg, rfi_server **out) {
   s->slot_plan.assign(n, nullptr);
   s->slot_bytes.assign(n, 0);
   s->slot_rec.assign(n, rfi_completion{});
+  s->slot_key.assign(n, GraphKey{});
   s->ctx.resize(n);
   for (int i = 0; i < n; ++i) {
     s->ctx[i] = SlotCtx{s, i};
@@ -268,6 +312,7 @@ int rfi_server_submit(rfi_server *srv, const rfi_request *req) {
     return set_error(RFI_ERR_INVALID_ARGUMENT, "vis and avg must be 16-byte aligned");
   size_t bytes = 0;
   if (rfi_plan_footprint(req->plan, &bytes) != RFI_OK) return set_error(RFI_ERR_INVALID_ARGUMENT, "bad plan");
+  if (req->stats != nullptr) bytes += rfi::plan_stats_bytes(req->plan);  // optional output
   if (bytes > srv->cfg.hbm_budget)
     return set_error(RFI_ERR_INVALID_ARGUMENT, "request footprint exceeds the server's HBM budget");
   {
@@ -311,6 +356,7 @@ int rfi_server_get_stats(const rfi_server *srv, rfi_server_stats *out) {
   std::lock_guard<std::mutex> lk(const_cast<rfi_server *>(srv)->mu);
   *out = srv->stats;
   out->graphs = srv->n_graphs.load();
+  out->graphs_cached = srv->n_cached.load();
   return RFI_OK;
 }
 
@@ -328,8 +374,8 @@ int rfi_server_destroy(rfi_server *srv) {
   (void)hipSetDevice(srv->cfg.device);
   for (hipStream_t st : srv->streams) (void)hipStreamSynchronize(st);
   for (auto &kv : srv->graphs) {
-    (void)hipGraphExecDestroy(kv.second.second);
-    (void)hipGraphDestroy(kv.second.first);
+    (void)hipGraphExecDestroy(kv.second.exec);
+    (void)hipGraphDestroy(kv.second.graph);
   }
   for (hipStream_t st : srv->streams) (void)hipStreamDestroy(st);
   (void)hipSetDevice(prev);

@@ -1,5 +1,6 @@
-// serve_policy.h -- the admission rule of the serving loop (rfi_server_*, include/rfi.h),
-// free of HIP so that it can be tested on a machine without a GPU.
+// serve_policy.h -- the admission rule and the graph-cache eviction rule of the serving
+// loop (rfi_server_*, include/rfi.h), free of HIP so that they can be tested on a machine
+// without a GPU.
 #pragma once
 
 #include <cstddef>
@@ -28,6 +29,22 @@ std::ptrdiff_t first_admissible(const Queue &queue, PlanOf plan_of, BytesOf byte
     ++i;
   }
   return -1;
+}
+
+// The cached graph to free when the cache is full: the least recently used entry that no
+// busy slot is replaying and that is not `keep` (the key about to be captured), or
+// cache.end() when every entry is in use.  `cache` maps keys to entries with a `last_use`
+// counter; `in_use(key)` tells whether a request on the device replays that key's graph.
+// Graphs of destroyed plans are never used again, so they are the first to go.
+template <class Cache, class Key, class InUse>
+typename Cache::const_iterator graph_to_evict(const Cache &cache, const Key &keep, InUse in_use) {
+  auto victim = cache.end();
+  for (auto it = cache.begin(); it != cache.end(); ++it) {
+    if (!(it->first < keep) && !(keep < it->first)) continue;
+    if (in_use(it->first)) continue;
+    if (victim == cache.end() || it->second.last_use < victim->second.last_use) victim = it;
+  }
+  return victim;
 }
 
 }  // namespace rfi

@@ -37,7 +37,7 @@ RFI_FLAG_SK_HIGH = 2
 RFI_FLAG_DS_RE = 4
 RFI_FLAG_DS_IM = 8
 
-STATE_RECORD_BYTES = 32
+STATE_RECORD_BYTES = 64
 
 # Every symbol include/rfi.h declares (checked by the CPU test suite).
 EXPORTS = (
@@ -82,7 +82,8 @@ class rfi_params(ctypes.Structure):
 
 class rfi_server_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("n_slots", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_uint64), ("use_graphs", ctypes.c_int32)]
+                ("hbm_budget", ctypes.c_uint64), ("use_graphs", ctypes.c_int32),
+                ("max_graphs", ctypes.c_int32)]
 
 
 class rfi_request(ctypes.Structure):
@@ -99,7 +100,8 @@ class rfi_completion(ctypes.Structure):
 class rfi_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("failed", ctypes.c_uint64), ("peak_inflight_bytes", ctypes.c_uint64),
-                ("peak_inflight", ctypes.c_int32), ("graphs", ctypes.c_int32)]
+                ("peak_inflight", ctypes.c_int32), ("graphs", ctypes.c_int32),
+                ("graphs_cached", ctypes.c_int32)]
 
 
 _lib = None
@@ -352,7 +354,8 @@ class Plan:
     def state(self):
         """Adaptive state as a numpy structured array [B][C/F] (n, mean[3], m2[3])."""
         import numpy as np
-        dt = np.dtype([("n", np.uint32), ("mean", np.float32, 3), ("m2", np.float32, 3), ("reserved", np.uint32)])
+        dt = np.dtype([("n", np.uint64), ("mean", np.float64, 3), ("m2", np.float64, 3), ("reserved", np.uint64)])
+        assert dt.itemsize == STATE_RECORD_BYTES
         a = np.zeros((self.B, self.G), dt)
         rfi_state_get(self.handle, a.view(np.uint8))
         return a
@@ -368,9 +371,9 @@ def _numel(shape):
 # --------------------------------------------------------------------------- serving loop
 
 def rfi_server_create(n_slots: int = 16, hbm_budget: int = 200 << 30, device: int = 0,
-                      use_graphs: bool = True) -> int:
+                      use_graphs: bool = True, max_graphs: int = 0) -> int:
     cfg = rfi_server_config(device=device, n_slots=n_slots, hbm_budget=hbm_budget,
-                            use_graphs=1 if use_graphs else 0)
+                            use_graphs=1 if use_graphs else 0, max_graphs=max_graphs)
     h = ctypes.c_void_p()
     _check(load_library().rfi_server_create(ctypes.byref(cfg), ctypes.byref(h)))
     return h.value
@@ -410,11 +413,14 @@ def rfi_server_destroy(server: Optional[int]) -> None:
 
 
 class Server:
-    """Serving loop with tensor checks; keeps each in-flight request's tensors alive."""
+    """Serving loop with tensor checks.  Each in-flight request holds its plan and tensors
+    until ``poll`` returns its completion: the scheduler thread reads the plan and the kernels
+    write its outputs and adaptive state after ``submit`` has returned, so a caller that drops
+    its own references early (``srv.submit(Plan(p), ...)``) must not free them."""
 
     def __init__(self, n_slots: int = 16, hbm_budget: int = 200 << 30, device: int = 0,
-                 use_graphs: bool = True):
-        self.handle = rfi_server_create(n_slots, hbm_budget, device, use_graphs)
+                 use_graphs: bool = True, max_graphs: int = 0):
+        self.handle = rfi_server_create(n_slots, hbm_budget, device, use_graphs, max_graphs)
         self._live = {}
 
     def now(self) -> float:
@@ -431,7 +437,7 @@ class Server:
             raise ValueError(f"tag {tag} is already in flight")
         # the server's streams wait on no other stream: finish whatever produced the inputs
         torch.cuda.current_stream(plan.device).synchronize()
-        self._live[tag] = (vis, out)
+        self._live[tag] = (plan, vis, out)
         try:
             rfi_server_submit(self.handle, plan.handle, vis, out["avg"], out["weight"], out.get("flags"),
                               out.get("stats"), self.now() if arrival is None else arrival, tag)

@@ -104,10 +104,13 @@ int main() {
   EXPECT(rfi_probe_copy(nullptr, nullptr, 16, nullptr) == RFI_ERR_INVALID_ARGUMENT);
   // serving: configuration and request checks
   rfi_server *srv = reinterpret_cast<rfi_server *>(0x1);
-  rfi_server_config cfg{0, 0, 1, 1};
+  rfi_server_config cfg{0, 0, 1, 1, 0};
   EXPECT(rfi_server_create(&cfg, &srv) == RFI_ERR_INVALID_ARGUMENT && srv == nullptr);
   cfg.n_slots = 4;
   cfg.hbm_budget = 0;
+  EXPECT(rfi_server_create(&cfg, &srv) == RFI_ERR_INVALID_ARGUMENT);
+  cfg.hbm_budget = 1;
+  cfg.max_graphs = -1;
   EXPECT(rfi_server_create(&cfg, &srv) == RFI_ERR_INVALID_ARGUMENT);
   EXPECT(rfi_server_create(nullptr, &srv) == RFI_ERR_INVALID_ARGUMENT);
   EXPECT(rfi_server_submit(nullptr, nullptr) == RFI_ERR_INVALID_ARGUMENT);

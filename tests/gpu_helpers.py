@@ -1,6 +1,10 @@
 """Helpers for the GPU parity tests: run librfi through the binding, compare with the oracle.
 
-Tolerances (relative error as |gpu - oracle| / max(1, |oracle|) for statistics):
+Tolerances (relative error as |gpu - oracle| / max(1, |oracle|) for statistics; r lies in
+[0, 1], so for r this is an absolute bound, and r is also held to the same tolerance as a true
+relative error |gpu - oracle| / |oracle| wherever |oracle| >= R_FLOOR = 0.05: below that the
+FP32 sum of W unit-vector components, whose error is about sqrt(W) 2^-24 per unit, cancels to
+a total too small for a relative bound):
   complex64 storage, FP32 arithmetic ............ 1e-5
   complex-half storage vs oracle on the same
     (FP16-rounded) input: arithmetic error ....... 1e-5
@@ -21,6 +25,7 @@ from paper_2412_14775_amd import rfi
 
 TOL_F32 = 1e-5
 TOL_F16_TOTAL = 3e-3
+R_FLOOR = 0.05
 
 
 def make_params(B, C, T, M, fmt="cf32", **kw):
@@ -118,6 +123,12 @@ def compare(gpu, vis_for_oracle, op: "oracle.Params", tol, thresholds=None, ref=
             e = stat_error(gpu[k], ref[k])
             rep[f"max_err_{k}"] = float(e.max()) if e.size else 0.0
             assert e.max(initial=0.0) <= tol, f"{label}: {k} max rel err {e.max():.3g} > {tol} at {np.unravel_index(np.argmax(e), e.shape)}"
+            if k != "tau":
+                o = np.asarray(ref[k], np.float64)
+                big = np.abs(o) >= R_FLOOR
+                rel = np.abs(np.asarray(gpu[k], np.float64)[big] - o[big]) / np.abs(o[big])
+                rep[f"max_relerr_{k}"] = float(rel.max()) if rel.size else 0.0
+                assert rel.max(initial=0.0) <= tol, f"{label}: {k} true relative error {rel.max():.3g} > {tol} (|r| >= {R_FLOOR})"
     if "flags" in gpu:
         thb = {k: (np.asarray(v)[..., None] if np.ndim(v) else v) for k, v in th.items()}
         near = near_threshold(ref, thb, tol)

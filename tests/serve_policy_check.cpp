@@ -119,8 +119,55 @@ static void simulation(unsigned seed) {
   EXPECT(queue.empty());
 }
 
+// The graph-cache eviction rule: least recently used, never a graph on the device, never the
+// key about to be captured; none when all are in use.
+struct Entry {
+  uint64_t last_use;
+};
+
+static void eviction_cases() {
+  std::map<int, Entry> cache{{1, {5}}, {2, {3}}, {3, {9}}, {4, {1}}};
+  auto none = [](int) { return false; };
+  EXPECT(rfi::graph_to_evict(cache, 99, none)->first == 4);            // least recently used
+  EXPECT(rfi::graph_to_evict(cache, 4, none)->first == 2);             // not the key being captured
+  auto busy4 = [](int k) { return k == 4; };
+  EXPECT(rfi::graph_to_evict(cache, 99, busy4)->first == 2);           // not one on the device
+  auto busy24 = [](int k) { return k == 2 || k == 4; };
+  EXPECT(rfi::graph_to_evict(cache, 1, busy24)->first == 3);
+  auto all = [](int) { return true; };
+  EXPECT(rfi::graph_to_evict(cache, 99, all) == cache.end());          // everything in use
+  std::map<int, Entry> empty;
+  EXPECT(rfi::graph_to_evict(empty, 1, none) == empty.end());
+  // a cache driven like the server's: capacity 3, random uses, some keys "on the device";
+  // the cache never holds an in-use key's eviction and stays at capacity
+  std::mt19937 rng(7);
+  std::map<int, Entry> c;
+  uint64_t clock = 0;
+  for (int step = 0; step < 2000; ++step) {
+    const int key = (int)(rng() % 8);
+    const int on_device = (int)(rng() % 8);
+    auto in_use = [&](int k) { return k == on_device; };
+    if (c.find(key) == c.end()) {
+      if (c.size() >= 3) {
+        auto v = rfi::graph_to_evict(c, key, in_use);
+        EXPECT(v != c.end());
+        if (v != c.end()) {
+          EXPECT(v->first != key && v->first != on_device);
+          for (auto &kv : c)  // nothing older that could have gone
+            EXPECT(kv.first == key || kv.first == on_device || kv.second.last_use >= v->second.last_use);
+          c.erase(v);
+        }
+      }
+      c[key] = Entry{0};
+    }
+    c[key].last_use = ++clock;
+    EXPECT(c.size() <= 3);
+  }
+}
+
 int main() {
   fixed_cases();
+  eviction_cases();
   for (unsigned seed = 1; seed <= 50; ++seed) simulation(seed);
   if (failures) {
     std::printf("%d failures\n", failures);

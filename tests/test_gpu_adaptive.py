@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_helpers import TOL_F32, compare, make_params, run_gpu, to_device
+from tests.gpu_helpers import TOL_F32, compare, make_params, near_threshold, run_gpu, stat_error, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -93,7 +93,7 @@ def test_state_checkpoint_roundtrip_and_reset():
     op, rp = make_params(B, C, T, M, options=oracle.OPT_ADAPTIVE, n_warm=2, kappa_sk=1.0, kappa_ds=1.0)
     plan = rfi.Plan(rp)
     st = plan.state()
-    assert st.nbytes == rfi.rfi_state_bytes(plan.handle) == B * C * 32
+    assert st.nbytes == rfi.rfi_state_bytes(plan.handle) == B * C * rfi.STATE_RECORD_BYTES == B * C * 64
     assert np.all(st["n"] == 0)
     # a resumed state with tight thresholds around tau = 1, r = 0: almost everything flagged
     st["n"] = 1000
@@ -109,3 +109,86 @@ def test_state_checkpoint_roundtrip_and_reset():
     torch.cuda.synchronize()
     assert np.all(plan.state()["n"] == 0)
     plan.close()
+
+
+def test_long_run_state_error():
+    """10^4 integrations of a small array (3 baselines x 8 channels, M = 16, 16 windows per
+    stream, complex64, pulsed polarised RFI in two channels), the state checked against the
+    oracle's float64 AdaptiveState every 1000 integrations (conditional parity: the oracle
+    merges the float64 statistics of the windows the GPU kept), and every integration's
+    flags against the oracle's thresholds of that moment (identical outside the excusal
+    band).  The state's error must stay within the statistics' 1e-5 over the whole run (a
+    float32 state would not; see test_adaptive_precision_cpu.py)."""
+    from paper_2412_14775_amd import rfi
+    import torch
+    B, C, T, M, K, CHUNK = 3, 8, 256, 16, 10000, 1000
+    op, rp = make_params(B, C, T, M, d=2.1, s_low=0.2, s_high=2.6, gamma=0.5, kappa_sk=3.0,
+                         kappa_ds=3.0, n_warm=64, options=oracle.OPT_ADAPTIVE)
+    plan = rfi.Plan(rp)
+    state = oracle.AdaptiveState((B, C))
+    nW = T // M
+    worst = dict(mean=0.0, m2=0.0, thr=0.0)
+    flagged = excused = 0
+    try:
+        avg = torch.empty((B, C, 4, 2), dtype=torch.float32, device="cuda:0")
+        weight = torch.empty((B, C), dtype=torch.float32, device="cuda:0")
+        flags = torch.empty((CHUNK, B, C, nW), dtype=torch.uint8, device="cuda:0")
+        stats = torch.empty((CHUNK, B, C, nW, 3), dtype=torch.float32, device="cuda:0")
+        for chunk in range(K // CHUNK):
+            Tc = T * CHUNK
+            sc = synth.Scene(2, C, Tc, seed=700 + chunk, rho=0.1,
+                             rfi=[synth.Rfi([2, 5], 6.0, 0.4, 0.2, synth.pulse_train(Tc, 900, 40, 7 * chunk),
+                                            f0=0.07)])
+            vis = synth.correlate(synth.make_voltages(sc))                  # [B, C, CHUNK T, 4]
+            vis = np.ascontiguousarray(vis.reshape(B, C, CHUNK, T, 4).transpose(2, 0, 1, 3, 4))
+            dev = to_device(vis, "cf32")                                     # [CHUNK, B, C, T, 4, 2]
+            print(f"chunk {chunk}: screening integrations {chunk * CHUNK}..{(chunk + 1) * CHUNK - 1}", flush=True)
+            for i in range(CHUNK):
+                plan.screen(dev[i], avg, weight, flags[i], stats[i])
+            torch.cuda.synchronize()
+            g_flags = flags.cpu().numpy()
+            g_stats = stats.cpu().numpy()
+            ref = oracle.screen(vis.reshape(CHUNK * B, C, T, 4), op)
+            o_stats = np.stack([ref["tau"], ref["r_re"], ref["r_im"]], -1).reshape(CHUNK, B, C, nW, 3)
+            for i in range(CHUNK):
+                th = state.thresholds(op)
+                thb = {k: np.asarray(v)[..., None] for k, v in th.items()}
+                o = {k: o_stats[i, ..., j] for j, k in enumerate(("tau", "r_re", "r_im"))}
+                o_flags = oracle.flag_bits(o["tau"], o["r_re"], o["r_im"], thb["s_low"], thb["s_high"],
+                                           thb["gamma"], op.options, thb["gamma_im"])
+                near = near_threshold(o, thb, TOL_F32)
+                bad = (o_flags != g_flags[i]) & ~near
+                assert not bad.any(), f"integration {chunk * CHUNK + i}: flags differ outside the band"
+                flagged += int((g_flags[i] != 0).sum())
+                excused += int(near.sum())
+                st_err = stat_error(g_stats[i], o_stats[i])
+                assert st_err.max() <= TOL_F32, f"integration {chunk * CHUNK + i}: statistic error {st_err.max():.3g}"
+                state.update(o_stats[i], g_flags[i] == 0)
+            g = plan.state()
+            assert np.array_equal(g["n"], state.n), f"after {(chunk + 1) * CHUNK}: window counts differ"
+            # true relative errors (r_im of the autocorrelations is exactly 0 on both sides)
+            rel = lambda a, b: float((np.abs(a - b) / np.maximum(np.abs(b), 1e-30)).max())  # noqa: E731
+            e_mean, e_m2 = rel(g["mean"], state.mean), rel(g["m2"], state.m2)
+            tg, to = _thresholds_of(g, op), state.thresholds(op)
+            e_thr = max(rel(tg[k], to[k]) for k in to)
+            worst = dict(mean=max(worst["mean"], e_mean), m2=max(worst["m2"], e_m2), thr=max(worst["thr"], e_thr))
+            print(f"after {(chunk + 1) * CHUNK} integrations ({int(state.n.min())}-{int(state.n.max())} clean "
+                  f"windows per stream): relative error of mean {e_mean:.2e}, M2 {e_m2:.2e}, "
+                  f"thresholds {e_thr:.2e}", flush=True)
+            assert e_mean <= TOL_F32 and e_m2 <= TOL_F32 and e_thr <= TOL_F32, worst
+        total = K * B * C * nW
+        print(f"long run: {K} integrations, flagged {flagged / total:.4f}, excused {excused / total:.2e}, "
+              f"worst relative error mean {worst['mean']:.2e}, M2 {worst['m2']:.2e}, "
+              f"thresholds {worst['thr']:.2e}")
+        assert 0.01 < flagged / total < 0.5           # the adaptive thresholds are exercised
+    finally:
+        plan.close()
+
+
+def _thresholds_of(g, op):
+    """The oracle's threshold rule applied to a state read back from the GPU."""
+    s = oracle.AdaptiveState(g.shape)
+    s.n = g["n"].astype(np.int64)
+    s.mean = g["mean"].astype(np.float64)
+    s.m2 = g["m2"].astype(np.float64)
+    return s.thresholds(op)

@@ -259,3 +259,97 @@ def test_direct_launch_mode_matches_graph_mode():
         plan.close()
     for name in ("avg", "weight", "flags", "stats"):
         assert np.array_equal(res[0][name], res[1][name], equal_nan=True), name
+
+
+def test_server_holds_the_plan_of_a_request_in_flight():
+    """A request whose Plan the caller does not keep (``srv.submit(rfi.Plan(p), ...)``) for a
+    future arrival: the server holds the plan until its completion is polled, so the scheduler
+    thread and the kernel never see a destroyed plan; the result equals a direct screen."""
+    import gc
+    import torch
+    from paper_2412_14775_amd import rfi
+    N, C = 4, 8
+    _, rp = make_params(N * (N + 1) // 2, C, T, M, "cf16", d=2.2, s_low=0.5, s_high=1.6, gamma=0.3)
+    vis = synth.to_cf16(synth.correlate(synth.make_voltages(synth.Scene(N, C, T, seed=21))))
+    dev = to_device(vis, "cf16")
+    ref_plan = rfi.Plan(rp)
+    ref = ref_plan.alloc_outputs(flags=True, stats=True)
+    ref_plan.screen(dev, ref["avg"], ref["weight"], ref["flags"], ref["stats"])
+    torch.cuda.synchronize()
+    out = ref_plan.alloc_outputs(flags=True, stats=True)
+    srv = rfi.Server(n_slots=2)
+    try:
+        srv.submit(rfi.Plan(rp), dev, out, arrival=srv.now() + 0.3, tag=5)
+        gc.collect()                               # the caller holds no reference to that plan
+        srv.drain(30)
+        done = srv.poll(10)
+        assert len(done) == 1 and done[0]["status"] == 0
+        got, want = _host(out), _host(ref)
+        for name in ("avg", "weight", "flags", "stats"):
+            assert np.array_equal(got[name], want[name], equal_nan=True), name
+    finally:
+        srv.close()
+        ref_plan.close()
+
+
+def test_graph_cache_is_bounded():
+    """With room for two graphs, five buffer sets of one plan served in turn (twice over) are
+    captured again after eviction, the cache never holds more than two graphs, and every
+    result equals the direct screen's."""
+    import torch
+    from paper_2412_14775_amd import rfi
+    N, C = 3, 8
+    _, rp = make_params(N * (N + 1) // 2, C, T, M, "cf16", d=2.2, s_low=0.5, s_high=1.6, gamma=0.3)
+    vis = synth.to_cf16(synth.correlate(synth.make_voltages(synth.Scene(N, C, T, seed=23))))
+    dev = to_device(vis, "cf16")
+    plan = rfi.Plan(rp)
+    ref = plan.alloc_outputs(flags=True, stats=False)
+    plan.screen(dev, ref["avg"], ref["weight"], ref["flags"], None)
+    torch.cuda.synchronize()
+    want = _host(ref)
+    outs = [plan.alloc_outputs(flags=True, stats=False) for _ in range(5)]
+    srv = rfi.Server(n_slots=2, max_graphs=2)
+    try:
+        tag = 0
+        for rnd in range(2):
+            for o in outs:
+                for t in o.values():
+                    if t is not None:
+                        t.zero_()
+                torch.cuda.synchronize()
+                srv.submit(plan, dev, o, tag=tag)
+                tag += 1
+                srv.drain(30)
+                assert srv.poll(10)[0]["status"] == 0
+                got = _host(o)
+                for name in ("avg", "weight", "flags"):
+                    assert np.array_equal(got[name], want[name], equal_nan=True), (rnd, name)
+                assert srv.stats()["graphs_cached"] <= 2
+        st = srv.stats()
+        assert st["graphs"] == 10, st              # every buffer set captured again after eviction
+    finally:
+        srv.close()
+        plan.close()
+
+
+def test_admission_counts_the_statistics_output():
+    """A request that writes per-window statistics needs [B][C/F][T/M][3] float32 more than the
+    plan's footprint: with a budget of the footprint alone it can never be admitted."""
+    from paper_2412_14775_amd import rfi
+    N, C = 3, 8
+    B = N * (N + 1) // 2
+    _, rp = make_params(B, C, T, M, "cf16", d=2.2, s_low=0.5, s_high=1.6, gamma=0.3)
+    plan = rfi.Plan(rp)
+    fp = plan.footprint()
+    out = plan.alloc_outputs(flags=True, stats=True)
+    dev = to_device(np.zeros((B, C, T, 4, 2), np.float16), "cf16")
+    srv = rfi.Server(n_slots=1, hbm_budget=fp + B * C * (T // M) * 12 - 1)
+    try:
+        with pytest.raises(rfi.RfiError):
+            srv.submit(plan, dev, out, tag=1)
+        srv.submit(plan, dev, {"avg": out["avg"], "weight": out["weight"], "flags": out["flags"]}, tag=2)
+        srv.drain(30)
+        assert srv.poll(10)[0]["status"] == 0
+    finally:
+        srv.close()
+        plan.close()
