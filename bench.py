@@ -38,7 +38,7 @@ N_STATIONS, N_CHANNELS, N_SAMPLES, BLOCK_M = 48, 64, 3072, 64
 SEED = 1
 # plan thresholds for M = 64 (null quantiles of this generator: SK 2.5 / 97.5 %, DS 95 %)
 PLAN = dict(sk_d=2.2, sk_low=0.656, sk_high=1.487, ds_gamma=0.202)
-CPU_SAMPLE_BASELINES = 900          # baselines (x all 64 channels): about 20 s of oracle CPU work
+CPU_SAMPLE_BASELINES = 600          # baselines (x all 64 channels): about 30 s of oracle CPU work
 
 
 def kernel_source_digest() -> str:
@@ -58,42 +58,114 @@ def algorithmic_bytes(n_streams: int, T: int, M: int, sample_bytes: int) -> int:
 # ----------------------------------------------------------------------------- CPU baseline
 
 _CPU_VIS = None
+_CPU_M = BLOCK_M
 
 
 def _oracle_chunk(bounds):
     import oracle
     b0, b1 = bounds
-    p = oracle.Params(M=BLOCK_M, d=PLAN["sk_d"], s_low=PLAN["sk_low"], s_high=PLAN["sk_high"],
+    p = oracle.Params(M=_CPU_M, d=PLAN["sk_d"], s_low=PLAN["sk_low"], s_high=PLAN["sk_high"],
                       gamma=PLAN["ds_gamma"])
     out = oracle.screen(_CPU_VIS[b0:b1], p)
     return int((out["flags"] != 0).sum())
 
 
+def _time_oracle(vis: np.ndarray, M: int, workers: int, per_task: int = 2) -> float:
+    """Seconds the oracle takes over ``vis`` [B, C, T, 4] in a pool of ``workers`` processes
+    (forked before any GPU use; ``per_task`` baselines per task)."""
+    global _CPU_VIS, _CPU_M
+    _CPU_VIS, _CPU_M = vis, M
+    chunks = [(i, min(i + per_task, vis.shape[0])) for i in range(0, vis.shape[0], per_task)]
+    try:
+        with mp.get_context("fork").Pool(workers) as pool:
+            pool.map(_oracle_chunk, chunks[:workers])              # warm the workers
+            t0 = time.perf_counter()
+            pool.map(_oracle_chunk, chunks, chunksize=1)
+            return time.perf_counter() - t0
+    finally:
+        _CPU_VIS = None
+
+
 def cpu_baseline(e: np.ndarray) -> dict:
-    """FP64 oracle on a fixed sample of the workload, in a process pool on the host's cores.
-    Data generation is outside the timed region; only the oracle's compute is timed."""
-    global _CPU_VIS
+    """FP64 oracle on bounded samples of two workloads, in a process pool over every core this
+    process may run on.  Data generation is outside the timed region; only the oracle's
+    compute is timed.
+      * the FP32 baseline (48 stations, 64 channels, 3072 samples, M = 64): a seeded sample of
+        CPU_SAMPLE_BASELINES of its 1176 baselines, all channels and samples;
+      * the 64-station mixed case (2080 baselines, 256 channels, M = 64): a seeded 1 % of its
+        (baseline, channel) streams (21 baselines, all channels), extrapolated as samples/s."""
+    try:
+        workers = len(os.sched_getaffinity(0))
+    except AttributeError:
+        workers = os.cpu_count() or 1
     rng = np.random.default_rng(1234)
     bl = np.sort(rng.choice(synth.n_baselines(N_STATIONS), CPU_SAMPLE_BASELINES, replace=False))
-    _CPU_VIS = synth.correlate(e, bl)                            # [Bs, C, T, 4] complex64
-    try:
-        avail = len(os.sched_getaffinity(0))
-    except AttributeError:
-        avail = os.cpu_count() or 1
-    cores = max(1, min(16, avail))
-    chunks = [(i, min(i + 2, len(bl))) for i in range(0, len(bl), 2)]
-    ctx = mp.get_context("fork")                                  # before any GPU use
-    with ctx.Pool(cores) as pool:
-        pool.map(_oracle_chunk, chunks[:cores])                   # warm the workers
-        t0 = time.perf_counter()
-        pool.map(_oracle_chunk, chunks, chunksize=1)
-        dt = time.perf_counter() - t0
-    n = _CPU_VIS.shape[0] * _CPU_VIS.shape[1] * _CPU_VIS.shape[2]
-    _CPU_VIS = None
-    return {"value": n / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
+    vis = synth.correlate(e, bl)                                   # [Bs, C, T, 4] complex64
+    n = vis.shape[0] * vis.shape[1] * vis.shape[2]
+    dt = _time_oracle(vis, BLOCK_M, workers)
+    del vis
+    sc3 = synth.scene_mixed(3)
+    bl3 = np.sort(np.random.default_rng(4321).choice(sc3.n_baselines, 21, replace=False))
+    vis3 = synth.correlate(synth.make_voltages(sc3), bl3)          # 1.0 % of the streams
+    n3 = vis3.shape[0] * vis3.shape[1] * vis3.shape[2]
+    dt3 = _time_oracle(vis3, 64, workers, per_task=1)
+    del vis3
+    return {"value": n / dt, "unit": "samples/s", "cores": workers, "kind": "oracle",
+            "host_cpu_count": os.cpu_count(),
             "sample": f"{len(bl)} of 1176 baselines x 64 channels x 3072 samples "
                       f"({n / 1e6:.1f} M samples, complex64, M=64), FP64 NumPy oracle, "
-                      f"{cores} worker processes, {dt:.2f} s wall"}
+                      f"{workers} worker processes (all cores this process may use; os.cpu_count() "
+                      f"= {os.cpu_count()}), {dt:.2f} s wall",
+            "mixed_case_c3": {"value": n3 / dt3, "unit": "samples/s", "cores": workers,
+                              "sample": f"21 of 2080 baselines x 256 channels x 3072 samples "
+                                        f"(1.0 % of the streams, {n3 / 1e6:.1f} M samples, M=64), "
+                                        f"{dt3:.2f} s wall; samples/s extrapolate to the whole "
+                                        f"26.2 GB integration"}}
+
+
+PREC_BASELINES = 16                 # seeded baselines (x all channels) for the precision block
+TF_PLAN = dict(sk_d=2.2, sk_low=0.42, sk_high=2.0, ds_gamma=0.40)   # 10 x 2 windows (W = 20)
+
+
+def precision_references(e: np.ndarray, e3000: np.ndarray) -> dict:
+    """FP64 oracle outputs of a seeded sample of baselines (one autocorrelation and crosses,
+    all channels) of the FP32-baseline workload (its complex64 bytes, and the same bytes
+    rounded to complex half) and of the 10 x 2 workload (3000 samples).  The GPU screens
+    exactly these bytes: bench.py writes them over the same baselines of the device arrays."""
+    import oracle
+    rng = np.random.default_rng(99)
+    B = synth.n_baselines(N_STATIONS)
+    bl = np.sort(np.concatenate([[0], rng.choice(np.arange(1, B), PREC_BASELINES - 1, replace=False)]))
+    v = synth.correlate(e, bl)
+    p = oracle.Params(M=BLOCK_M, d=PLAN["sk_d"], s_low=PLAN["sk_low"], s_high=PLAN["sk_high"],
+                      gamma=PLAN["ds_gamma"])
+    keep = ("tau", "r_re", "r_im", "flags")
+    ref32 = oracle.screen(v, p)
+    ref16 = oracle.screen(synth.to_cf16(v), p)
+    v3000 = synth.correlate(e3000, bl)
+    p10 = oracle.Params(M=10, F=2, d=TF_PLAN["sk_d"], s_low=TF_PLAN["sk_low"], s_high=TF_PLAN["sk_high"],
+                        gamma=TF_PLAN["ds_gamma"])
+    ref10 = oracle.screen(v3000, p10)
+    return dict(bl=bl, vis=v, vis3000=v3000, ref32={k: ref32[k] for k in keep},
+                ref16={k: ref16[k] for k in keep}, ref10={k: ref10[k] for k in keep})
+
+
+def stat_errors(stats: np.ndarray, ref: dict) -> dict:
+    """max and p99 over windows of |gpu - oracle| / max(1, |oracle|) per statistic (NaN on
+    both sides counts as equal)."""
+    out = {}
+    for k, name in enumerate(("tau", "r_re", "r_im")):
+        g = stats[..., k].astype(np.float64)
+        o = ref[name]
+        err = np.where(np.isnan(g) & np.isnan(o), 0.0, np.abs(g - o) / np.maximum(1.0, np.abs(o)))
+        out[name] = {"max": float(np.max(err)), "p99": float(np.percentile(err, 99))}
+    return out
+
+
+def flag_disagreement(a: np.ndarray, b: np.ndarray) -> dict:
+    """Windows whose flag bits differ, and windows flagged on one side only (the flag mask,
+    the measure of the paper's Section 4.3 comparison)."""
+    return {"bits": float(np.mean(a != b)), "mask": float(np.mean((a != 0) != (b != 0)))}
 
 
 # ----------------------------------------------------------------------------- GPU
@@ -101,6 +173,7 @@ def cpu_baseline(e: np.ndarray) -> dict:
 def time_form(plan, vis, outs, stream, steps, warmup):
     """Warm up, then time `steps` screens with HIP events on the launch stream."""
     import torch
+    stream.wait_stream(torch.cuda.current_stream())              # inputs written on torch's stream
     for _ in range(warmup):
         plan.screen(vis, outs["avg"], outs["weight"], outs["flags"], None, stream=stream)
     torch.cuda.synchronize()
@@ -120,6 +193,27 @@ def time_form(plan, vis, outs, stream, steps, warmup):
     per = np.array([a.elapsed_time(b) for a, b in ev])          # ms per screen
     total_ms = t_begin.elapsed_time(t_end)
     return per, total_ms, wall
+
+
+def put_baselines(vis_dev, bl, vis_host):
+    """Write host visibilities [len(bl), C, T, 4] complex64 over baselines ``bl`` of the device
+    array [B, C, T, 4, 2] float32 (so that the GPU screens the oracle's exact input bytes)."""
+    import torch
+    a = np.ascontiguousarray(vis_host.astype(np.complex64)).view(np.float32).reshape(vis_host.shape + (2,))
+    vis_dev[torch.as_tensor(bl, device=vis_dev.device)] = torch.from_numpy(a).to(vis_dev.device)
+
+
+def sampled_precision(plan, vis, bl, ref):
+    """One screen with statistics (outside any timed region); the sampled baselines'
+    statistics and flags against the FP64 oracle's ``ref``."""
+    import torch
+    outs = plan.alloc_outputs(flags=True, stats=True)
+    plan.screen(vis, outs["avg"], outs["weight"], outs["flags"], outs["stats"])
+    torch.cuda.synchronize()
+    idx = torch.as_tensor(bl, device=vis.device)
+    st = outs["stats"][idx].cpu().numpy()
+    fl = outs["flags"][idx].cpu().numpy()
+    return {"statistic_error": stat_errors(st, ref), "flags_vs_oracle": flag_disagreement(fl, ref["flags"])}
 
 
 def probe_bandwidth(vis_bytes_tensor, nbytes, stream, reps=10):
@@ -169,9 +263,12 @@ def stored_traffic(digest: str):
     return t.get("cf32_bytes_per_launch")
 
 
-def tf_window_form(steps: int, warmup: int):
+def tf_window_form(steps: int, warmup: int, refs=None):
     """The paper's own window shape, 10 time samples x 2 channels (W = 20), on a 48-station,
-    64-channel integration of 3000 samples (T divisible by 10), complex64 and complex half."""
+    64-channel integration of 3000 samples (T divisible by 10), complex64 and complex half, and
+    the paper's mixed precision (Tables 3-4).  With ``refs`` (precision_references) the
+    sampled baselines carry the oracle's input bytes, and each form's statistics and flags
+    are compared with the FP64 oracle's after its timing."""
     import torch
     from paper_2412_14775_amd import rfi
     dev = torch.device("cuda:0")
@@ -181,19 +278,25 @@ def tf_window_form(steps: int, warmup: int):
     vis32 = torch.empty((B, C, T, 4, 2), dtype=torch.float32, device=dev)
     synth.correlate_torch(e, vis32, "cf32")
     del e
+    if refs is not None:
+        put_baselines(vis32, refs["bl"], refs["vis3000"])
+    torch.cuda.synchronize()
     stream = torch.cuda.Stream(device=dev)
     res = {"window": "10 x 2", "samples": T}
     flags = {}
+    prec = {}
     for name, fmt, sb, opt in (("cf32", rfi.RFI_VIS_CF32, 32, 0), ("cf16", rfi.RFI_VIS_CF16, 16, 0),
                                ("cf32_paper_mixed", rfi.RFI_VIS_CF32, 32, rfi.RFI_OPT_PAPER_MIXED)):
         vis = vis32 if fmt == rfi.RFI_VIS_CF32 else vis32.to(torch.float16)
         params = rfi.rfi_params_default(n_stations=N_STATIONS, n_baselines=B, n_channels=C,
                                         n_samples=T, block_m=10, block_f=2, vis_format=fmt, options=opt,
-                                        sk_d=2.2, sk_low=0.42, sk_high=2.0, ds_gamma=0.40)
+                                        **TF_PLAN)
         plan = rfi.Plan(params)
         outs = plan.alloc_outputs(flags=True, stats=False)
         with torch.cuda.stream(stream):
             per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup)
+        if refs is not None:
+            prec[name] = sampled_precision(plan, vis, refs["bl"], refs["ref10"])
         plan.close()
         flags[name] = outs["flags"].clone()
         alg = B * C * (T * sb + 36) + B * (C // 2) * (T // 10)
@@ -202,9 +305,11 @@ def tf_window_form(steps: int, warmup: int):
                      "achieved_GBs": alg / (per.mean() * 1e-3) / 1e9,
                      "hbm_frac": alg / (per.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del vis
-    res["paper_mixed_flag_disagreement_vs_cf32"] = float(
-        (flags["cf32_paper_mixed"] != flags["cf32"]).float().mean().item())
-    res["cf16_flag_disagreement_vs_cf32"] = float((flags["cf16"] != flags["cf32"]).float().mean().item())
+    f32 = flags["cf32"].cpu().numpy()
+    res["paper_mixed_flag_disagreement_vs_cf32"] = flag_disagreement(flags["cf32_paper_mixed"].cpu().numpy(), f32)
+    res["cf16_flag_disagreement_vs_cf32"] = flag_disagreement(flags["cf16"].cpu().numpy(), f32)
+    if refs is not None:
+        res["vs_fp64_oracle"] = prec
     del vis32
     torch.cuda.empty_cache()
     return res
@@ -373,9 +478,14 @@ def main(argv=None):
 
     scene = synth.scene_fp32_baseline(SEED, N_STATIONS, N_CHANNELS, N_SAMPLES)
     e = synth.make_voltages(scene)                                # [N, C, T, 2] complex64
-    cpu = None if args.no_cpu_baseline else cpu_baseline(e)
-    if cpu is not None:
+    cpu = refs = None
+    if not args.no_cpu_baseline:                                  # host work, before any GPU use
+        cpu = cpu_baseline(e)
         progress(f"cpu baseline: {cpu['value']:.3g} samples/s ({cpu['sample']})")
+        e3000 = synth.make_voltages(synth.scene_fp32_baseline(SEED, N_STATIONS, N_CHANNELS, 3000))
+        refs = precision_references(e, e3000)
+        del e3000
+        progress(f"oracle references of {len(refs['bl'])} sampled baselines done")
 
     import torch
     from paper_2412_14775_amd import rfi
@@ -387,12 +497,14 @@ def main(argv=None):
     e_dev = torch.from_numpy(e).to(dev)
     vis32 = torch.empty((B, C, T, 4, 2), dtype=torch.float32, device=dev)
     synth.correlate_torch(e_dev, vis32, "cf32")
-    vis16 = vis32.to(torch.float16)
     del e_dev
+    if refs is not None:
+        put_baselines(vis32, refs["bl"], refs["vis"])
+    vis16 = vis32.to(torch.float16)
     torch.cuda.synchronize()
 
     stream = torch.cuda.Stream(device=dev)                       # default priority
-    forms = {}
+    forms, all_flags, prec = {}, {}, {}
     for name, vis, fmt, sb in (("cf32", vis32, rfi.RFI_VIS_CF32, 32), ("cf16", vis16, rfi.RFI_VIS_CF16, 16)):
         params = rfi.rfi_params_default(n_stations=N_STATIONS, n_baselines=B, n_channels=C,
                                         n_samples=T, block_m=M, vis_format=fmt, **PLAN)
@@ -401,6 +513,11 @@ def main(argv=None):
         with torch.cuda.stream(stream):
             per, total_ms, wall = time_form(plan, vis, outs, stream, args.steps, args.warmup)
         flagged = float((outs["flags"] != 0).float().mean().item())
+        all_flags[name] = outs["flags"].cpu().numpy()
+        if refs is not None:
+            prec[name] = sampled_precision(plan, vis, refs["bl"], refs["ref32"])
+            if name == "cf16":
+                prec["cf16_on_fp16_bytes"] = sampled_precision(plan, vis, refs["bl"], refs["ref16"])
         plan.close()
         alg = algorithmic_bytes(n_streams, T, M, sb)
         avg_s = per.mean() * 1e-3
@@ -422,7 +539,7 @@ def main(argv=None):
     del vis32, vis16
     torch.cuda.empty_cache()
     progress(f"read probe: {probe:.0f} GB/s")
-    tf = tf_window_form(max(10, args.steps // 4), max(2, args.warmup // 4))
+    tf = tf_window_form(max(10, args.steps // 4), max(2, args.warmup // 4), refs)
     progress("10 x 2 windows done")
     long_w = long_window_form(max(10, args.steps // 4), max(2, args.warmup // 4))
     progress("one-window-per-integration form done")
@@ -466,6 +583,18 @@ def main(argv=None):
         "long_window": long_w,
         "mixed_case_cf16": mixed,
         "serving": serve,
+        "precision": None if refs is None else {
+            "sample": f"{len(refs['bl'])} seeded baselines (one autocorrelation) x 64 channels of the "
+                      "FP32-baseline workload and of the 10 x 2 workload; the GPU screens the oracle's "
+                      "exact input bytes",
+            "statistic_error": "|gpu - oracle| / max(1, |oracle|) over windows (tolerance 1e-5 "
+                               "complex64, 3e-3 complex half against the complex64 input)",
+            "cf32_vs_fp64": prec["cf32"],
+            "cf16_vs_fp64_on_complex64_input": prec["cf16"],
+            "cf16_vs_fp64_on_fp16_bytes": prec["cf16_on_fp16_bytes"],
+            "cf16_vs_cf32_all_streams": flag_disagreement(all_flags["cf16"], all_flags["cf32"]),
+            "tf_window_10x2_vs_fp64": tf.get("vs_fp64_oracle"),
+        },
         "flagged_frac": f32["flagged_frac"],
         "kernel_source_digest": digest,
     }
