@@ -91,3 +91,27 @@ def test_binary16_unit_vector_sums_by_hand():
     assert float(r_im[0]) == 0.0 and float(tau[0]) == 0.0
     I, Q, U, V = oracle.stokes(win)
     assert abs(oracle.ds_r(Q.real, U.real, V.real, 2.0 ** -23)[0] - 0.0885503) < 1e-6
+
+
+def test_mixed_flags_on_the_48_station_10x2_workload():
+    """The paper's mixed form against the FP64 oracle on 24 seeded baselines of the 48-station,
+    64-channel, 10 x 2 workload (pulsed RFI of random polarisation, 0-20 dB, in 5 % of the
+    channels).  Flag masks (flagged or not: the measure of Section 4.3's comparison) differ in
+    well under 1 % of windows.  Flag bits differ in about 1 %: where W S2 passes the binary16
+    range (strong RFI) the ratio of group 7 is inf / inf or inf, so tau is NaN or infinite and
+    the window carries SK_LOW where the FP64 oracle sets SK_HIGH -- flagged either way."""
+    import synth
+    e = synth.make_voltages(synth.scene_fp32_baseline(1, 48, 64, 3000))
+    bl = np.sort(np.random.default_rng(5).choice(1176, 24, replace=False))
+    vis = synth.correlate(e, bl)
+    p = Params(M=10, F=2, d=2.2, s_low=0.42, s_high=2.0, gamma=0.40)
+    a = oracle.screen(vis, p)
+    b = oracle.screen_mixed(vis, p)
+    mask = float(np.mean((a["flags"] != 0) != (b["flags"] != 0)))
+    bits = a["flags"] != b["flags"]
+    overflow = ~np.isfinite(b["tau"])
+    print(f"masks differ {mask:.5f}, bits differ {bits.mean():.5f}, non-finite mixed tau {overflow.mean():.5f}")
+    assert mask < 0.002
+    assert np.mean(a["flags"][overflow] != 0) > 0.99         # overflowing windows are RFI the FP64 oracle flags
+    # bit differences outside those windows are near-threshold statistics only
+    assert np.mean(bits & ~overflow) < 0.002
