@@ -43,6 +43,8 @@ def check_cf16(vis, M, label, **kw):
     op, gpu = screen_both(vis, M, "cf16", **kw)
     rep_a = compare(gpu, synth.to_cf16(vis), op, TOL_F32, label=label + " (fp16 input)")
     rep_t = compare(gpu, vis, op, cf16_total_tolerance(vis, op), label=label + " (original input)")
+    print(f"{label}: arithmetic error " + ", ".join(f"{k} {rep_a['max_err_' + k]:.2e}" for k in ("tau", "r_re", "r_im"))
+          + "; total error " + ", ".join(f"{k} {rep_t['max_err_' + k]:.2e}" for k in ("tau", "r_re", "r_im")))
     return rep_a, rep_t
 
 
