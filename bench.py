@@ -176,13 +176,41 @@ def flag_disagreement(a: np.ndarray, b: np.ndarray) -> dict:
 
 # ----------------------------------------------------------------------------- GPU
 
-def time_form(plan, vis, outs, stream, steps, warmup):
-    """Warm up, then time `steps` screens with HIP events on the launch stream."""
+SETTLE_MS = 30.0                    # GPU time of a form's launches before its timed launches
+
+
+SETTLE_LOG: dict = {}               # extra warm-up launches per timed form
+
+
+def time_form(plan, vis, outs, stream, steps, warmup, key):
+    """Warm up, then time `steps` screens with HIP events on the launch stream.
+
+    Warm-up is `warmup` launches and then, untimed as well, as many more as it takes for the
+    form's launches to have run SETTLE_MS of GPU time: the first few milliseconds of a form
+    after a switch (other kernels, host work, a fresh array) run up to twice as slow while the
+    GPU's clocks settle (profiles/screen_fp32_baseline.md, launch-to-launch spread).  The
+    count of those extra launches is logged in SETTLE_LOG under ``key``."""
     import torch
     stream.wait_stream(torch.cuda.current_stream())              # inputs written on torch's stream
+    w0 = torch.cuda.Event(enable_timing=True)
+    w1 = torch.cuda.Event(enable_timing=True)
+    w0.record(stream)
     for _ in range(warmup):
         plan.screen(vis, outs["avg"], outs["weight"], outs["flags"], None, stream=stream)
+    w1.record(stream)
     torch.cuda.synchronize()
+    done_ms = w0.elapsed_time(w1)
+    extra = 0
+    while done_ms < SETTLE_MS:
+        n = max(1, int(np.ceil((SETTLE_MS - done_ms) / max(done_ms / max(warmup, 1), 0.05))))
+        w0.record(stream)
+        for _ in range(n):
+            plan.screen(vis, outs["avg"], outs["weight"], outs["flags"], None, stream=stream)
+        w1.record(stream)
+        torch.cuda.synchronize()
+        done_ms += w0.elapsed_time(w1)
+        extra += n
+    SETTLE_LOG[key] = extra
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t_begin = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
@@ -300,7 +328,7 @@ def tf_window_form(steps: int, warmup: int, refs=None):
         plan = rfi.Plan(params)
         outs = plan.alloc_outputs(flags=True, stats=False)
         with torch.cuda.stream(stream):
-            per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup)
+            per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup, f"tf_window.{name}")
         if refs is not None:
             prec[name] = sampled_precision(plan, vis, refs["bl"], refs["ref10"])
         plan.close()
@@ -343,7 +371,7 @@ def long_window_form(steps: int, warmup: int):
         plan = rfi.Plan(params)
         outs = plan.alloc_outputs(flags=True, stats=False)
         with torch.cuda.stream(stream):
-            per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup)
+            per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup, f"long_window.{name}")
         plan.close()
         alg = algorithmic_bytes(B * C, T, T, sb)
         res[name] = {"samples_per_s": B * C * T * steps / (total_ms * 1e-3),
@@ -377,7 +405,7 @@ def mixed_case_form(steps: int, warmup: int):
         plan = rfi.Plan(params)
         outs = plan.alloc_outputs(flags=True, stats=False)
         with torch.cuda.stream(stream):
-            per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup)
+            per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup, f"mixed_case_cf16.M{M}")
         plan.close()
         alg = algorithmic_bytes(B * C, T, M, 16)
         res[f"M{M}"] = {"samples_per_s": B * C * T * steps / (total_ms * 1e-3), "kernel_ms_mean": float(per.mean()),
@@ -517,7 +545,7 @@ def main(argv=None):
         plan = rfi.Plan(params)
         outs = plan.alloc_outputs(flags=True, stats=False)
         with torch.cuda.stream(stream):
-            per, total_ms, wall = time_form(plan, vis, outs, stream, args.steps, args.warmup)
+            per, total_ms, wall = time_form(plan, vis, outs, stream, args.steps, args.warmup, name)
         flagged = float((outs["flags"] != 0).float().mean().item())
         all_flags[name] = outs["flags"].cpu().numpy()
         if refs is not None:
@@ -565,6 +593,7 @@ def main(argv=None):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle": {"min_ms_of_launches_before_timing": SETTLE_MS, "extra_warmup_launches": SETTLE_LOG},
         "ms_per_step": f32["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",

@@ -59,19 +59,30 @@ constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kMaxTiledLog2M = 12;  // tiled kernels exist for M = 2 .. 4096
 
 // The kernel that screens windows of M samples x F channels in storage format `fmt`:
-// tiled (F = 1, M a power of two <= 4096), windowed (M = K S, K <= 8, F S <= 64), long
-// (F = 1, M more than a quarter of a step: 64 complex64 / 128 complex-half samples),
-// otherwise one lane per window.  The paper's mixed precision exists only in the windowed
-// kernel with complex64 storage (kNone elsewhere).  The tiled and long kernels may split a
+// tiled (F = 1, M a power of two <= 4096); windowed (runs of C <= 8 samples per lane,
+// ceil(M / C) F <= 64 lanes per window) when its layout is exact, when the long kernel does
+// not apply, or when the layout fills at least kPadOverLong of its lane slots; long (F = 1,
+// M more than half a step: 128 complex64 / 256 complex-half samples); otherwise one lane per
+// window (windows wider than 64 lanes).  The paper's mixed precision exists only in the windowed kernel on exact
+// layouts with complex64 storage (kNone elsewhere).  The tiled and long kernels may split a
 // stream into window-aligned segments (one wave each).
 enum KernelKind { kTiled, kWindows, kLong, kGeneric, kNone };
 KernelKind kernel_for(int M, int F, int fmt, bool mixed);
 
+// Lane layout of the windowed kernel: C samples per lane, padded (pad) or exact, and the
+// share of its lane slots that hold samples.  C = 0: the windowed kernel does not apply.
+struct WindowsLayout {
+  int C;
+  bool pad;
+  double share;
+};
+WindowsLayout windows_layout(int M, int F, int fmt, bool mixed);
+constexpr int kPadMaxC32 = 5;            // padded complex64 layouts: at most 5 samples per lane
+constexpr double kPadOverLong = 0.75;    // padded layouts this full go before the long kernel
+
 // Kernel selection (kernel_for).  Returns hipErrorInvalidValue when no kernel matches.
 hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream);
 bool tiled_supports(int M);
-// Samples per lane of the windowed kernel for (M, F), or 0 when it does not apply.
-int windows_samples_per_lane(int M, int F);
 
 // Records the thread's last error (read back by rfi_last_error) and returns `code`.
 int set_error(int code, const char *fmt, ...);

@@ -476,15 +476,15 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a, int U
 // each window that lies wholly in the step (up to three), the others those that open
 // the next window (at most 62 lanes), so the step costs K + 1 sample slots instead of
 // the 2 K of two masked passes over every lane, plus one wave reduction per window
-// it closes.  Each lane adds its
-// step sums plainly for kFold steps before folding them into the window sums, so
-// no lane sums more than kFold K samples in a row whatever M is.
-constexpr int kLongMaxWhole = 3;  // windows wholly inside one step: M > a quarter of a step
-
+// it closes.  Each lane adds its step sums plainly for kFold steps before folding them into
+// the window sums, so no lane sums more than kFold K samples in a row whatever M is.
+//
 // MAXW: the most windows that lie wholly inside one step for this M (1 when 2 M > a step,
-// 2 when 3 M > a step, else kLongMaxWhole): the edge step is unrolled for that many, and the
-// longer windows keep the shorter code (MAXW 1 instead of 3: 3 % faster at M = 500-1000, 9 % at
-// complex64 M = 131; MAXW 2 instead of 3: 1-1.5 % at M = 97-251).
+// 2 when 3 M > a step, else 3 above a quarter of a step): the edge step is unrolled for that
+// many.  The launch takes only windows of more than half a step (MAXW = 1): every shorter
+// length has a lane layout in the windowed kernel (runs of up to 8 samples, padded), which
+// screens it 1-45 % faster than this kernel did (complex half M = 131-500 0.51-0.69 -> 0.73-0.80
+// of the HBM peak, complex64 M = 67-193 0.62-0.80 -> 0.82-0.83).
 template <int FMT, int MAXW>
 __global__ void __launch_bounds__(kBlock) screen_long(const ScreenArgs a) {
   constexpr int K = FMT == FMT_CF32 ? 4 : 8;
@@ -697,39 +697,46 @@ __device__ __forceinline__ void mixed_statistics(const ScreenArgs &a, const floa
   r_im = r16(tot[5], tot[6], tot[7]);
 }
 
-// Windows of M = K S time samples x F channels, K <= 8, F S <= 64 lanes per
-// window (any M with such a factorisation, and every F > 1 shape the tiled kernel
-// does not take).  One wave per channel group.  A window owns L lanes, L = F S
-// rounded up to a power of two; lane l = (j L + f S + s) owns the K consecutive
-// samples s of channel f of window j of the step, so a lane stays on one channel
-// and keeps one masked sum.  A step covers 64 / L windows: for each channel a
-// contiguous run of their samples, loaded coalesced (channel-major) into the
-// wave's LDS tile and read back per lane.  When F S is not a power of two (GEN,
-// e.g. M = 100 = 4 x 25 on 32 lanes) the L - F S lanes left over in each group
-// neither read nor add, and the channel sums at the end are masked wave sums.
-template <int FMT, int K, int F, bool MIXED, bool GEN>
+// Windows of M time samples x F channels on lane groups: each channel of a window is
+// cut into S runs of C consecutive samples (C <= 8, F S <= 64), one lane per run, and a
+// window owns L lanes, F S rounded up to a power of two; lane l = (j L + f S + s) owns run
+// s of channel f of window j of the step, so a lane stays on one channel and keeps one
+// masked sum.  A step covers 64 / L windows: for each channel a contiguous run of their
+// samples, loaded coalesced (channel-major) into the wave's LDS tile and read back per
+// lane, then summed over the L lanes of each window with a DPP butterfly.
+//   PAD = false: M = C S exactly and F S = L (every lane holds C samples of its window);
+//       the tile holds the step's pieces in load order.
+//   PAD = true: any M with S = ceil(M / C); the last run of each channel holds
+//       M - (S - 1) C samples and the L - F S lanes left over in each group neither read
+//       nor add.  In the tile each channel of a window takes S C samples, the samples past
+//       M are zeros (written once; a zero sample adds exactly zero to every window sum and
+//       raw sum), so every lane reads C samples without tests.  Each lane's load offsets and
+//       tile slots are fixed for the kernel and computed once; the step offset is a scalar.
+//       The channel sums at the end are masked wave sums.
+template <int FMT, int C, int F, bool MIXED, bool PAD>
 __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
   constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
   constexpr int PPS = SB / 16;                  // 16-byte pieces per sample
-  constexpr int P = K * PPS;                    // pieces per lane per step
-  constexpr int CH_PIECES = kWave * P / F;      // pieces of one channel per step (F S = L)
-  constexpr int CH_SAMPLES = kWave * K / F;     // samples of one channel per step (F S = L)
+  constexpr int P = C * PPS;                    // pieces per lane per step (at most, PAD)
+  constexpr int CH_PIECES = kWave * P / F;      // pieces of one channel per step (!PAD)
+  constexpr int CH_SAMPLES = kWave * C / F;     // samples of one channel per step (!PAD)
+  static_assert(!(MIXED && PAD), "the paper's mixed precision runs on whole lane groups");
   __shared__ u32x4 tile[kWavesPerBlock][kWave * P];
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
   const int64_t group = (int64_t)blockIdx.x * kWavesPerBlock + wave;
   const bool active = group < a.n_groups;
-  const int S = a.M / K;                        // lanes per channel of a window
+  const int S = PAD ? (a.M + C - 1) / C : a.M / C;   // lanes per channel of a window
   const int FS = F * S;                         // lanes that hold samples
   int L = FS;                                   // lanes per window
-  if constexpr (GEN) L = 1 << (32 - __builtin_clz(FS - 1));
+  if constexpr (PAD) L = FS > 1 ? 1 << (32 - __builtin_clz(FS - 1)) : 1;
   const int g = lane % L;
-  const bool act = !GEN || g < FS;              // lane holds samples
+  const bool act = !PAD || g < FS;              // lane holds samples
   const int j = lane / L, f = act ? g / S : 0, s = act ? g % S : 0;
   const int wps = kWave / L;                    // windows per step
-  const int ch_samples = GEN ? wps * a.M : CH_SAMPLES;
-  const int ch_pieces = ch_samples * PPS;
+  const int ch_samples = PAD ? wps * a.M : CH_SAMPLES;    // samples of one channel per step
+  const int ch_tile = PAD ? wps * S * C * PPS : CH_PIECES; // tile pieces of one channel
 
   StreamAcc<1> acc{};                           // this lane's channel: masked sums, kept, moments
   if (active) {
@@ -740,32 +747,56 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
     const int n_steps = (a.nW + wps - 1) / wps;
     u32x4 *my_tile = tile[wave];
     u32x4 buf[P];
-    auto issue = [&](int step) {
+    // Piece i of a step is piece q = i 64 + lane of the step's F channel runs (channel-major),
+    // q < n_load: its byte offset in the group (the step adds ch_samples SB as a scalar) and,
+    // PAD, its tile slot (otherwise slot q).  Both are fixed for the kernel.  A piece past the
+    // end of a channel (ragged last step) belongs to no valid window: it reads the next channel
+    // of the group, or zeros past the group's buffer (hardware bounds check).
+    int voff[P], slot[PAD ? P : 1];
+    const int n_load = F * ch_samples * PPS;    // !PAD: 64 P
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        const int q = i * kWave + lane;         // piece of the step, channel-major
-        const int ch = GEN ? q / ch_pieces : q / CH_PIECES;
-        const int r = GEN ? q - ch * ch_pieces : q % CH_PIECES;
-        // pieces past the end of the channel (ragged last step) belong to no valid
-        // window, nor do those past the F channels of a GEN step
-        const bool inside = (!GEN || ch < F) && step * ch_samples + r / PPS < a.T;
-        const unsigned off = (unsigned)(ch * a.T + step * ch_samples) * SB + (unsigned)(r * 16);  // may pass 2^31 when !inside
-        buf[i] = inside ? __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming))
-                        : u32x4{0u, 0u, 0u, 0u};
+    for (int i = 0; i < P; ++i) {
+      const int q = i * kWave + lane;
+      voff[i] = 0;
+      if constexpr (PAD) {
+        slot[i] = -1;
+        my_tile[i * kWave + lane] = u32x4{0u, 0u, 0u, 0u};  // the padding stays zero
       }
+      if (q < n_load) {
+        const int ch = q / (ch_samples * PPS), r = q - ch * ch_samples * PPS;
+        const int t = r / PPS, h = r - t * PPS;  // sample of the channel run, half of it
+        voff[i] = (ch * a.T + t) * SB + h * 16;  // < F T SB < 2^31
+        if constexpr (PAD) {
+          const int w = t / a.M, o = t - w * a.M;  // window of the step, sample of the window
+          slot[i] = ch * ch_tile + (w * S * C + o) * PPS + h;
+        }
+      }
+    }
+    auto issue = [&](int step) {
+      const int soff = step * ch_samples * SB;
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        if (!PAD || slot[i] >= 0)
+          buf[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i], soff, kLoadStreaming));
     };
-    const int my_piece = act ? f * ch_pieces + (j * S + s) * P : 0;
+    const int my_piece = act ? f * ch_tile + (j * S * C + s * C) * PPS : 0;
     issue(0);
     for (int step = 0; step < n_steps; ++step) {
       wave_lds_order();
 #pragma unroll
-      for (int i = 0; i < P; ++i) my_tile[i * kWave + lane] = buf[i];
+      for (int i = 0; i < P; ++i) {
+        if constexpr (PAD) {
+          if (slot[i] >= 0) my_tile[slot[i]] = buf[i];
+        } else {
+          my_tile[i * kWave + lane] = buf[i];
+        }
+      }
       wave_lds_order();
       if (step + 1 < n_steps) issue(step + 1);
       float ws[8] = {}, wr[8] = {};
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (!act) break;                        // GEN: a lane left over in its group
+      for (int k = 0; k < C; ++k) {
+        if (!act) break;                        // PAD: a lane left over in its group
         if constexpr (FMT == FMT_CF32) {
           const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k]);
           const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k + 1]);
@@ -794,8 +825,8 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
     }
   }
   // masked sums: reduce over the lanes of each channel
-  float chan[GEN ? F : 1][8];
-  if constexpr (GEN) {                          // channel bits are not lane bits: masked wave sums
+  float chan[PAD ? F : 1][8];
+  if constexpr (PAD) {                          // channel bits are not lane bits: masked wave sums
 #pragma unroll
     for (int c = 0; c < F; ++c)
 #pragma unroll
@@ -824,7 +855,7 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
     out[1] = f32x4{v[4] * inv, v[5] * inv, v[6] * inv, v[7] * inv};
     a.weight[stream] = kept * a.invT;
   };
-  if constexpr (GEN) {
+  if constexpr (PAD) {
     if (lane == 0)
 #pragma unroll
       for (int c = 0; c < F; ++c) write_channel(c, chan[c]);
@@ -908,6 +939,16 @@ __global__ void __launch_bounds__(kBlock) screen_generic(const ScreenArgs a) {
 // 12 waves by its registers already.
 constexpr unsigned kCf32OccupancyPad = 7680;
 
+// Blocks per CU of the complex-half tiled kernel, set by unused dynamic LDS (0: the four its
+// registers and LDS allow; kCf32OccupancyPad: three; 22528 bytes: two), by log2 M.  Timed on
+// 48 x 64 and 64 x 256 arrays with the variants alternating launch by launch: two blocks are
+// 3-5 % faster than four at M = 8-64 and 1024-4096, three blocks 2-3 % faster at M = 4 and
+// 128-512 (where two lose up to 4.5 %), four best at M = 2 (two: -6.5 %).  As with the
+// complex64 kernel, fewer streams read at once suit HBM better, up to the point where too
+// few loads are in flight.
+constexpr unsigned kTiledCf16Pad[kMaxTiledLog2M + 1] = {0u, 0u, 7680u, 22528u, 22528u, 22528u, 22528u,
+                                                        7680u, 7680u, 7680u, 22528u, 22528u, 22528u};
+
 // The persistent complex64 tiled launch: three blocks per CU, each holding at most this many
 // flag bytes in LDS (33 KiB static + 19 KiB < 160 KiB / 3).  Complex64 with flags, one
 // segment per stream: +1 % at M = 64, +4 % at M = 16.  Complex half lost 1-4 % in this form
@@ -932,7 +973,7 @@ hipError_t launch_tiled(const ScreenArgs &a, hipStream_t stream) {
   }
   const int64_t units = a.n_groups * a.n_seg;
   const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
-  const unsigned pad = FMT == FMT_CF32 ? kCf32OccupancyPad : 0u;
+  const unsigned pad = FMT == FMT_CF32 ? kCf32OccupancyPad : kTiledCf16Pad[LOG2M];
   hipLaunchKernelGGL((screen_tiled<FMT, LOG2M, false>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a, 0);
   return hipGetLastError();
 }
@@ -969,12 +1010,8 @@ hipError_t launch_long(const ScreenArgs &a, hipStream_t stream) {
   const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
   const unsigned pad = FMT == FMT_CF16 && a.M >= 2048 ? kLongCf16RareEdgePad : 0u;
   const int spi = kWave * (FMT == FMT_CF32 ? 4 : 8);
-  if (2 * a.M > spi)
-    hipLaunchKernelGGL((screen_long<FMT, 1>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
-  else if (3 * a.M > spi)
-    hipLaunchKernelGGL((screen_long<FMT, 2>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
-  else
-    hipLaunchKernelGGL((screen_long<FMT, kLongMaxWhole>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
+  if (2 * a.M <= spi) return hipErrorInvalidValue;  // kernel_for sends these to the windowed kernel
+  hipLaunchKernelGGL((screen_long<FMT, 1>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a);
   return hipGetLastError();
 }
 
@@ -991,40 +1028,40 @@ hipError_t launch_generic(const ScreenArgs &a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int FMT, int K, bool MIXED, bool GEN>
+template <int FMT, int C, bool MIXED, bool PAD>
 hipError_t launch_windows_k(const ScreenArgs &a, hipStream_t stream) {
   const int64_t blocks = (a.n_groups + kWavesPerBlock - 1) / kWavesPerBlock;
   const dim3 grid((unsigned)blocks), block(kBlock);
   switch (a.F) {
-    case 1: hipLaunchKernelGGL((screen_windows<FMT, K, 1, MIXED, GEN>), grid, block, 0, stream, a); break;
-    case 2: hipLaunchKernelGGL((screen_windows<FMT, K, 2, MIXED, GEN>), grid, block, 0, stream, a); break;
-    case 4: hipLaunchKernelGGL((screen_windows<FMT, K, 4, MIXED, GEN>), grid, block, 0, stream, a); break;
+    case 1: hipLaunchKernelGGL((screen_windows<FMT, C, 1, MIXED, PAD>), grid, block, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((screen_windows<FMT, C, 2, MIXED, PAD>), grid, block, 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((screen_windows<FMT, C, 4, MIXED, PAD>), grid, block, 0, stream, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-// GEN (F S not a power of two) exists only outside the paper's mixed precision.
-template <int FMT, int K, bool MIXED>
-hipError_t launch_windows_g(bool gen, const ScreenArgs &a, hipStream_t stream) {
+// PAD (padded runs or partial lane groups) exists only outside the paper's mixed precision.
+template <int FMT, int C, bool MIXED>
+hipError_t launch_windows_p(bool pad, const ScreenArgs &a, hipStream_t stream) {
   if constexpr (MIXED)
-    return gen ? hipErrorInvalidValue : launch_windows_k<FMT, K, true, false>(a, stream);
+    return pad ? hipErrorInvalidValue : launch_windows_k<FMT, C, true, false>(a, stream);
+  else if constexpr (FMT == FMT_CF32 && C > kPadMaxC32)  // windows_layout never pads these
+    return pad ? hipErrorInvalidValue : launch_windows_k<FMT, C, false, false>(a, stream);
   else
-    return gen ? launch_windows_k<FMT, K, false, true>(a, stream) : launch_windows_k<FMT, K, false, false>(a, stream);
+    return pad ? launch_windows_k<FMT, C, false, true>(a, stream) : launch_windows_k<FMT, C, false, false>(a, stream);
 }
 
 template <int FMT, bool MIXED>
-hipError_t launch_windows(int K, const ScreenArgs &a, hipStream_t stream) {
-  const int FS = a.F * (a.M / K);
-  const bool gen = (FS & (FS - 1)) != 0;
-  switch (K) {
-    case 2: return launch_windows_g<FMT, 2, MIXED>(gen, a, stream);
-    case 3: return launch_windows_g<FMT, 3, MIXED>(gen, a, stream);
-    case 4: return launch_windows_g<FMT, 4, MIXED>(gen, a, stream);
-    case 5: return launch_windows_g<FMT, 5, MIXED>(gen, a, stream);
-    case 6: return launch_windows_g<FMT, 6, MIXED>(gen, a, stream);
-    case 7: return launch_windows_g<FMT, 7, MIXED>(gen, a, stream);
-    case 8: return launch_windows_g<FMT, 8, MIXED>(gen, a, stream);
+hipError_t launch_windows(const WindowsLayout &w, const ScreenArgs &a, hipStream_t stream) {
+  switch (w.C) {
+    case 2: return launch_windows_p<FMT, 2, MIXED>(w.pad, a, stream);
+    case 3: return launch_windows_p<FMT, 3, MIXED>(w.pad, a, stream);
+    case 4: return launch_windows_p<FMT, 4, MIXED>(w.pad, a, stream);
+    case 5: return launch_windows_p<FMT, 5, MIXED>(w.pad, a, stream);
+    case 6: return launch_windows_p<FMT, 6, MIXED>(w.pad, a, stream);
+    case 7: return launch_windows_p<FMT, 7, MIXED>(w.pad, a, stream);
+    case 8: return launch_windows_p<FMT, 8, MIXED>(w.pad, a, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1080,36 +1117,36 @@ bool tiled_supports(int M) {
   return l >= 1 && l <= kMaxTiledLog2M;
 }
 
-int windows_samples_per_lane(int M, int F) {
-  // K in 2..8 dividing M with F S <= 64 (S = M / K) that uses the largest share of the
-  // power-of-two lane group it needs, F S / L; among equals the largest K (fewer lanes,
-  // more samples per lane).  A factorisation with S a power of two uses all its lanes
-  // and wins whenever there is one.
-  int best = 0;
-  double best_use = 0.0;
-  for (int K = 8; K >= 2; --K) {
-    if (M % K != 0 || F * (M / K) > kWave) continue;
-    const int FS = F * (M / K);
+WindowsLayout windows_layout(int M, int F, int fmt, bool mixed) {
+  // Runs of C = 2..8 samples per lane, S = ceil(M / C) runs per channel, F S <= 64 lanes
+  // rounded up to a power of two L: the layout that fills the largest share M F / (L C) of
+  // its lane slots; among equals the largest C (fewer lanes per window, fewer window
+  // reductions per sample).  An exact layout (M = C S and F S = L: share 1) runs without
+  // padding; a padded one keeps per-piece offsets and slots in registers, which complex64
+  // storage (two pieces per sample) affords up to C = kPadMaxC32.
+  WindowsLayout best{0, false, 0.0};
+  for (int C = 8; C >= 2; --C) {
+    const int S = (M + C - 1) / C;
+    const int FS = F * S;
+    if (FS > kWave) continue;
     int L = 1;
     while (L < FS) L *= 2;
-    const double use = (double)FS / L;
-    if (use > best_use) {
-      best_use = use;
-      best = K;
-    }
+    const bool exact = S * C == M && FS == L;
+    if (!exact && (mixed || (fmt == FMT_CF32 && C > kPadMaxC32))) continue;
+    const double share = (double)M * F / ((double)L * C);
+    if (share > best.share + 1e-12) best = WindowsLayout{C, !exact, share};
   }
   return best;
 }
 
 KernelKind kernel_for(int M, int F, int fmt, bool mixed) {
-  if (mixed) {  // the windowed kernel with whole power-of-two lane groups, complex64 storage
-    const int K = windows_samples_per_lane(M, F);
-    const int FS = K > 0 ? F * (M / K) : 0;
-    return fmt == FMT_CF32 && K > 0 && (FS & (FS - 1)) == 0 ? kWindows : kNone;
-  }
+  if (mixed)  // the windowed kernel on whole lane groups, complex64 storage
+    return fmt == FMT_CF32 && windows_layout(M, F, fmt, true).C > 0 ? kWindows : kNone;
   if (F == 1 && tiled_supports(M)) return kTiled;
-  if (windows_samples_per_lane(M, F) > 0) return kWindows;
-  if (F == 1 && (kLongMaxWhole + 1) * M > kWave * (fmt == FMT_CF32 ? 4 : 8)) return kLong;
+  const WindowsLayout w = windows_layout(M, F, fmt, false);
+  const bool long_ok = F == 1 && 2 * M > kWave * (fmt == FMT_CF32 ? 4 : 8);
+  if (w.C > 0 && (!w.pad || !long_ok || w.share >= kPadOverLong)) return kWindows;
+  if (long_ok) return kLong;
   return kGeneric;
 }
 
@@ -1121,9 +1158,10 @@ hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream) {
       return cf32 ? dispatch_tiled<FMT_CF32>(l, a, stream) : dispatch_tiled<FMT_CF16>(l, a, stream);
     }
     case kWindows: {
-      const int K = windows_samples_per_lane(a.M, a.F);
-      if (a.options & kOptPaperMixed) return launch_windows<FMT_CF32, true>(K, a, stream);
-      return cf32 ? launch_windows<FMT_CF32, false>(K, a, stream) : launch_windows<FMT_CF16, false>(K, a, stream);
+      const bool mixed = (a.options & kOptPaperMixed) != 0;
+      const WindowsLayout w = windows_layout(a.M, a.F, fmt, mixed);
+      if (mixed) return launch_windows<FMT_CF32, true>(w, a, stream);
+      return cf32 ? launch_windows<FMT_CF32, false>(w, a, stream) : launch_windows<FMT_CF16, false>(w, a, stream);
     }
     case kLong: return cf32 ? launch_long<FMT_CF32>(a, stream) : launch_long<FMT_CF16>(a, stream);
     case kGeneric: return cf32 ? launch_generic<FMT_CF32>(a, stream) : launch_generic<FMT_CF16>(a, stream);

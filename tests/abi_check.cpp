@@ -42,13 +42,23 @@ static void kernel_choice() {
   EXPECT(kernel_for(64, 2, c32, false) == kWindows && kernel_for(384, 1, c32, false) == kWindows);
   EXPECT(kernel_for(300, 1, c32, false) == kWindows && kernel_for(300, 1, c16, false) == kWindows);  // 5 x 60 lanes
   EXPECT(kernel_for(600, 1, c16, false) == kLong && kernel_for(3000, 1, c16, false) == kLong);
-  EXPECT(kernel_for(500, 1, c16, false) == kLong && kernel_for(257, 1, c16, false) == kLong);   // > half a step
-  EXPECT(kernel_for(131, 1, c32, false) == kLong && kernel_for(131, 1, c16, false) == kLong);   // > a quarter
-  EXPECT(kernel_for(67, 1, c32, false) == kLong && kernel_for(127, 1, c16, false) == kGeneric);
-  EXPECT(kernel_for(100, 1, c32, false) == kWindows && kernel_for(15, 2, c16, false) == kWindows);  // 25 of 32, 6 of 8 lanes
-  EXPECT(kernel_for(8192, 2, c32, false) == kGeneric && kernel_for(61, 1, c32, false) == kGeneric);  // no K <= 8 fits
-  EXPECT(windows_samples_per_lane(100, 1) == 4 && windows_samples_per_lane(10, 2) == 5 &&
-         windows_samples_per_lane(48, 1) == 6 && windows_samples_per_lane(50, 1) == 2);
+  EXPECT(kernel_for(513, 1, c16, false) == kLong && kernel_for(321, 1, c32, false) == kLong);  // > 64 runs of 8 / 5
+  // padded runs fill at least 3/4 of their lane slots: before the long kernel
+  EXPECT(kernel_for(500, 1, c16, false) == kWindows && kernel_for(257, 1, c16, false) == kWindows);
+  EXPECT(kernel_for(131, 1, c32, false) == kWindows && kernel_for(131, 1, c16, false) == kWindows);
+  EXPECT(kernel_for(67, 1, c32, false) == kWindows && kernel_for(127, 1, c16, false) == kWindows);
+  EXPECT(kernel_for(100, 1, c32, false) == kWindows && kernel_for(15, 2, c16, false) == kWindows);
+  EXPECT(kernel_for(61, 1, c32, false) == kWindows && kernel_for(61, 1, c16, false) == kWindows);
+  EXPECT(kernel_for(8192, 2, c32, false) == kGeneric && kernel_for(300, 2, c16, false) == kGeneric);  // > 64 lanes
+  EXPECT(kernel_for(129, 4, c16, false) == kGeneric && kernel_for(200, 4, c32, false) == kGeneric);
+  // lane layouts: (samples per lane, padded, share of lane slots)
+  const WindowsLayout l100 = windows_layout(100, 1, c16, false), l100b = windows_layout(100, 1, c32, false);
+  EXPECT(l100.C == 7 && l100.pad && l100.share > 0.89 && l100.share < 0.90);   // 15 runs on 16 lanes
+  EXPECT(l100b.C == 4 && l100b.pad && l100b.share == 25.0 / 32.0);            // complex64: C <= 5 padded
+  EXPECT(windows_layout(10, 2, c16, false).C == 5 && !windows_layout(10, 2, c16, false).pad);
+  EXPECT(windows_layout(48, 1, c32, false).C == 6 && !windows_layout(48, 1, c32, false).pad);
+  EXPECT(windows_layout(50, 1, c16, false).C == 7 && windows_layout(61, 1, c16, false).C == 8);
+  EXPECT(windows_layout(100, 1, c32, true).C == 0 && windows_layout(10, 2, c32, true).C == 5);
   EXPECT(kernel_for(1000, 2, c16, false) == kGeneric);
   EXPECT(kernel_for(10, 2, c32, true) == kWindows && kernel_for(64, 1, c32, true) == kWindows);
   EXPECT(kernel_for(10, 2, c16, true) == kNone && kernel_for(1024, 1, c32, true) == kNone);

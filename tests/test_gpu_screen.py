@@ -177,15 +177,14 @@ def test_half_sums_are_exact():
                                    (500, 5000, 2), (450, 4050, 1), (131, 1310, 2), (193, 3860, 1),
                                    (251, 2510, 1), (127, 1270, 2), (97, 1940, 1), (67, 1340, 2)])
 def test_long_windows(fmt, M, T, N):
-    """Windows of more than half a step (128 complex64 / 256 complex-half samples) that are not
-    powers of two up to 4096 and have no factor K <= 8 with S <= 64 (the long-window kernel):
-    edges fall anywhere inside a step, steps are ragged at the stream end, and few streams split
-    over waves.  A window one sample longer or shorter than a whole number of steps (513, 1023
-    complex half; 257, 511 complex64) walks the edge through every offset of the step; 3072 and
-    768 (complex64) end every window with a step; windows shorter than a step (131-511 complex
-    half, 67-193 complex64) put up to three whole windows and two edges into a step.  M = 300
-    (5 x 60) goes to the windowed kernel instead, and 67-127 of complex half to the
-    one-lane-per-window kernel; they stay here as cross-checks."""
+    """Windows of more than a quarter of a step (64 complex64 / 128 complex-half samples) that
+    are not powers of two up to 4096 and take more than 64 runs of 5 (complex64) or 8 (complex
+    half) samples (the long-window kernel): edges fall anywhere inside a step, steps are ragged at
+    the stream end, and few streams split over waves.  A window one sample longer or shorter
+    than a whole number of steps (513, 1023 complex half; 511 complex64) walks the edge through
+    every offset of the step; 3072 and 768 (complex64) end every window with a step.  The
+    shorter lengths (67-511 complex half, 67-320 complex64, and 300 = 5 x 60) go to the windowed
+    kernel with padded runs or partial lane groups instead; they stay here as cross-checks."""
     vis = scene_vis(N, 2, T, seed=M + T, duty=(500, 60))
     if fmt == "cf32":
         op, gpu = screen_both(vis, M, **thresholds_for(M))
@@ -195,32 +194,38 @@ def test_long_windows(fmt, M, T, N):
 
 
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
-@pytest.mark.parametrize("M,T", [(61, 1220), (113, 1130)])
-def test_one_lane_per_window_lengths(fmt, M, T):
-    """Prime lengths of at most a quarter of a step (complex64 61; complex half 61 and 113) have
-    no factor K <= 8 with S <= 64: one lane per window, its sums compensated.  Complex64 113 is
-    the long-window kernel's (more than 64 samples)."""
-    vis = scene_vis(2, 3, T, seed=M * 3, duty=(120, 25))
+@pytest.mark.parametrize("M,F,C,T", [(300, 2, 4, 1200), (129, 4, 4, 516)])
+def test_one_lane_per_window_lengths(fmt, M, F, C, T):
+    """Windows wider than 64 lanes of runs of at most 8 samples (300 x 2, 129 x 4): one lane per
+    window, its sums compensated."""
+    vis = scene_vis(2, C, T, seed=M * 3 + F, duty=(120, 25))
     if fmt == "cf32":
-        op, gpu = screen_both(vis, M, **thresholds_for(M))
-        compare(gpu, vis, op, TOL_F32, label=f"one lane cf32 M={M}")
+        op, gpu = screen_both(vis, M, F=F, **thresholds_for(M * F))
+        compare(gpu, vis, op, TOL_F32, label=f"one lane cf32 {M}x{F}")
     else:
-        check_cf16(vis, M, f"one lane cf16 M={M}", **thresholds_for(M))
+        check_cf16(vis, M, f"one lane cf16 {M}x{F}", F=F, **thresholds_for(M * F))
 
 
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
 @pytest.mark.parametrize("M,F,C,T", [(100, 1, 2, 1000), (300, 1, 2, 3000), (50, 1, 2, 1000), (15, 2, 4, 600),
-                                     (9, 2, 4, 450), (25, 4, 8, 500), (100, 2, 4, 1000)])
+                                     (9, 2, 4, 450), (25, 4, 8, 500), (100, 2, 4, 1000),
+                                     (100, 1, 2, 1300), (50, 1, 2, 1350), (61, 1, 3, 1281), (67, 1, 2, 1005),
+                                     (97, 1, 2, 679), (113, 1, 2, 1017), (127, 1, 2, 1143), (131, 1, 2, 655),
+                                     (193, 1, 2, 965), (251, 1, 2, 753), (257, 1, 2, 771), (500, 1, 2, 1500),
+                                     (100, 2, 4, 1300), (33, 2, 4, 990)])
 def test_windows_on_partial_lane_groups(fmt, M, F, C, T):
-    """Windows whose F S lanes are not a power of two (M = 100 = 4 x 25 on 32 lanes, 300 = 5 x 60
-    on 64, 15 x 2 = 5 x (3 x 2) on 8, ...): the left-over lanes of each group must neither read
-    nor add, and the channel sums are masked wave sums."""
-    vis = scene_vis(2, C, T, seed=M * 10 + F, duty=(120, 25))
+    """Windows cut into runs of C samples per lane that do not fill whole power-of-two lane
+    groups: the last run of each channel padded with zeros (M = 100 as 15 runs of 7 on 16 lanes
+    in complex half, 61 as 8 runs of 8, 500 as 63 runs of 8 on 64, ...) or the left-over lanes of
+    a group idle (complex64 M = 100 = 4 x 25 on 32 lanes, 300 = 5 x 60 on 64).  Left-over lanes
+    must neither read nor add, padding must add nothing, and the channel sums are masked wave
+    sums; the second half of the cases ends on a ragged step (fewer windows than a step holds)."""
+    vis = scene_vis(2, C, T, seed=M * 10 + F + T, duty=(120, 25))
     if fmt == "cf32":
         op, gpu = screen_both(vis, M, F=F, **thresholds_for(M * F))
-        compare(gpu, vis, op, TOL_F32, label=f"partial groups cf32 {M}x{F}")
+        compare(gpu, vis, op, TOL_F32, label=f"partial groups cf32 {M}x{F} T={T}")
     else:
-        check_cf16(vis, M, f"partial groups cf16 {M}x{F}", F=F, **thresholds_for(M * F))
+        check_cf16(vis, M, f"partial groups cf16 {M}x{F} T={T}", F=F, **thresholds_for(M * F))
 
 
 # ----------------------------------------------------------------------------- time x frequency windows
