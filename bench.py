@@ -300,7 +300,8 @@ def stored_traffic(digest: str):
 def tf_window_form(steps: int, warmup: int, refs=None):
     """The paper's own window shape, 10 time samples x 2 channels (W = 20), on a 48-station,
     64-channel integration of 3000 samples (T divisible by 10), complex64 and complex half, and
-    the paper's mixed precision (Tables 3-4).  With ``refs`` (precision_references) the
+    the paper's mixed precision (Tables 3-4); then M = 100 on the same array (complex64 and
+    complex half), a length with no exact lane layout.  With ``refs`` (precision_references) the
     sampled baselines carry the oracle's input bytes, and each form's statistics and flags
     are compared with the FP64 oracle's after its timing."""
     import torch
@@ -344,6 +345,26 @@ def tf_window_form(steps: int, warmup: int, refs=None):
     res["cf16_flag_disagreement_vs_cf32"] = flag_disagreement(flags["cf16"].cpu().numpy(), f32)
     if refs is not None:
         res["vs_fp64_oracle"] = prec
+    # a window length with no exact lane layout on the same array: M = 100 time samples (complex
+    # half: 15 runs of 7 samples on 16 lanes, the last run zero-padded; complex64: 25 runs of 4
+    # on 32 lanes)
+    res["window_100"] = {}
+    for name, fmt, sb in (("cf32", rfi.RFI_VIS_CF32, 32), ("cf16", rfi.RFI_VIS_CF16, 16)):
+        vis = vis32 if fmt == rfi.RFI_VIS_CF32 else vis32.to(torch.float16)
+        params = rfi.rfi_params_default(n_stations=N_STATIONS, n_baselines=B, n_channels=C, n_samples=T,
+                                        block_m=100, vis_format=fmt, sk_d=2.2, sk_low=0.55, sk_high=1.55,
+                                        ds_gamma=0.16)
+        plan = rfi.Plan(params)
+        outs = plan.alloc_outputs(flags=True, stats=False)
+        with torch.cuda.stream(stream):
+            per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup, f"window_100.{name}")
+        plan.close()
+        alg = algorithmic_bytes(B * C, T, 100, sb)
+        res["window_100"][name] = {"samples_per_s": B * C * T * steps / (total_ms * 1e-3),
+                                   "kernel_ms_mean": float(per.mean()),
+                                   "achieved_GBs": alg / (per.mean() * 1e-3) / 1e9,
+                                   "hbm_frac": alg / (per.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del vis
     del vis32
     torch.cuda.empty_cache()
     return res

@@ -25,7 +25,7 @@ def build_command(out: str) -> list:
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
             "-I", os.path.join(ROOT, "include"),
-            *[os.path.join(CSRC, s) for s in SOURCES], "-o", out]
+            *[os.path.join(CSRC, s) for s in SOURCES], "-lrocprofiler-sdk-roctx", "-o", out]
 
 
 def build(verbose: bool = False) -> str:

@@ -1028,14 +1028,22 @@ hipError_t launch_generic(const ScreenArgs &a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+constexpr int kFourBlocksLds = 33024;  // LDS per block that leaves room for four (160 KiB / 5 < this)
+
 template <int FMT, int C, bool MIXED, bool PAD>
 hipError_t launch_windows_k(const ScreenArgs &a, hipStream_t stream) {
   const int64_t blocks = (a.n_groups + kWavesPerBlock - 1) / kWavesPerBlock;
   const dim3 grid((unsigned)blocks), block(kBlock);
+  // exact complex-half layouts of 5 or more samples per lane: at most four blocks per CU (unused
+  // dynamic LDS past 160 KiB / 5): 1-2 % faster than the five their registers allow (10 x 2, 5 x 4,
+  // M = 20, 48); padded layouts and runs of 3 are not
+  constexpr int tile_bytes = kWavesPerBlock * kWave * C * (FMT == FMT_CF32 ? 2 : 1) * 16;
+  constexpr unsigned pad = FMT == FMT_CF16 && !PAD && !MIXED && C >= 5 && tile_bytes < kFourBlocksLds
+                               ? (unsigned)(kFourBlocksLds - tile_bytes) : 0u;
   switch (a.F) {
-    case 1: hipLaunchKernelGGL((screen_windows<FMT, C, 1, MIXED, PAD>), grid, block, 0, stream, a); break;
-    case 2: hipLaunchKernelGGL((screen_windows<FMT, C, 2, MIXED, PAD>), grid, block, 0, stream, a); break;
-    case 4: hipLaunchKernelGGL((screen_windows<FMT, C, 4, MIXED, PAD>), grid, block, 0, stream, a); break;
+    case 1: hipLaunchKernelGGL((screen_windows<FMT, C, 1, MIXED, PAD>), grid, block, pad, stream, a); break;
+    case 2: hipLaunchKernelGGL((screen_windows<FMT, C, 2, MIXED, PAD>), grid, block, pad, stream, a); break;
+    case 4: hipLaunchKernelGGL((screen_windows<FMT, C, 4, MIXED, PAD>), grid, block, pad, stream, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -7,11 +7,19 @@
 // hipGraph of its screen step on its slot's stream, followed by a host
 // callback that timestamps completion and frees the slot.  The callback takes
 // the server mutex only briefly and never calls into HIP.
+//
+// Tracing: each admission is a roctx range ("rfi_server admit tag=... slot=..." around the
+// graph launch or capture and the callback's enqueue), each capture and each completion a
+// roctx mark, so a rocprofv3 --marker-trace run lines requests up with their kernels.  With
+// no profiler attached the calls do nothing.
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <chrono>
+#include <cinttypes>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <atomic>
@@ -115,6 +123,9 @@ void rfi_server::on_done(void *p) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     rfi_completion rec = s->slot_rec[c->slot];
+    char msg[80];
+    std::snprintf(msg, sizeof msg, "rfi_server done tag=%" PRIu64 " slot=%d", rec.tag, c->slot);
+    roctxMarkA(msg);
     rec.done = s->now();
     s->done.push_back(rec);
     s->slot_busy[c->slot] = false;
@@ -156,6 +167,7 @@ int rfi_server::launch(int slot, const rfi_request &r) {
     }
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
+    roctxMarkA("rfi_server capture graph");
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return set_error(RFI_ERR_DEVICE, "hipStreamBeginCapture failed");
     const int rc = rfi_screen(r.plan, r.vis, r.avg, r.weight, r.flags, r.stats, st);
@@ -226,9 +238,13 @@ void rfi_server::run() {
       rec.status = RFI_OK;
       // HIP calls run without the mutex: the completion callback takes it
       lk.unlock();
+      char msg[80];
+      std::snprintf(msg, sizeof msg, "rfi_server admit tag=%" PRIu64 " slot=%d", p.req.tag, slot);
+      roctxRangePushA(msg);
       int rc = launch(slot, p.req);
       if (rc == RFI_OK && hipLaunchHostFunc(streams[slot], &rfi_server::on_done, &ctx[slot]) != hipSuccess)
         rc = set_error(RFI_ERR_DEVICE, "hipLaunchHostFunc failed");
+      roctxRangePop();
       if (rc != RFI_OK) (void)hipStreamSynchronize(streams[slot]);
       lk.lock();
       if (rc != RFI_OK) {  // no callback was enqueued: complete the request here

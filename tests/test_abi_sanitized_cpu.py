@@ -24,7 +24,8 @@ def test_host_abi_under_address_and_undefined_behaviour_sanitizers(tmp_path):
            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            os.path.join(CSRC, "screen.hip"), os.path.join(CSRC, "api.hip"), os.path.join(CSRC, "serve.hip"),
-           os.path.join(CSRC, "calibrate.cpp"), os.path.join(ROOT, "tests", "abi_check.cpp"), "-o", exe]
+           os.path.join(CSRC, "calibrate.cpp"), os.path.join(ROOT, "tests", "abi_check.cpp"),
+           "-lrocprofiler-sdk-roctx", "-o", exe]
     build = subprocess.run(cmd, capture_output=True, text=True)
     assert build.returncode == 0, build.stderr[-4000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
