@@ -14,6 +14,8 @@ stream), the read-bandwidth probe, and the FP64 oracle timed on the host's
 cores on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py --shapes cf16:64 cf16:10x2 cf32:10x2m ... [--steps K] [--warmup W]
+         (times only the listed window shapes; for profiling single kernels)
 """
 from __future__ import annotations
 
@@ -512,6 +514,68 @@ def serving(seconds: float, rate: float):
     }
 
 
+def parse_shape(spec: str):
+    """'fmt:M[xF][m][@T]' -> (fmt, M, F, mixed, T): storage format cf32 or cf16, window of M time
+    samples x F channels, 'm' for the paper's mixed precision, T samples per stream (default 3072
+    when M divides it, else 3000)."""
+    fmt, rest = spec.split(":")
+    T = None
+    if "@" in rest:
+        rest, t = rest.split("@")
+        T = int(t)
+    mixed = rest.endswith("m")
+    rest = rest.rstrip("m")
+    M, F = (int(x) for x in rest.split("x")) if "x" in rest else (int(rest), 1)
+    if T is None:
+        T = N_SAMPLES if N_SAMPLES % M == 0 else 3000
+    if fmt not in ("cf32", "cf16") or T % M or N_CHANNELS % F:
+        raise ValueError(f"bad shape {spec!r}")
+    return fmt, M, F, mixed, T
+
+
+def time_shapes(specs, steps: int, warmup: int) -> list:
+    """Each listed window shape on the 48-station, 64-channel array (synthetic, as the FP32
+    baseline), one screen with flags per launch: `warmup` launches plus the settling launches,
+    then `steps` timed with HIP events on the launch stream.  For profiling single kernels
+    (rocprofv3 runs over this mode launch nothing else of the screen)."""
+    import torch
+    from paper_2412_14775_amd import rfi
+    dev = torch.device("cuda:0")
+    arrays, out = {}, []
+    stream = torch.cuda.Stream(device=dev)
+    for spec in specs:
+        fmt, M, F, mixed, T = parse_shape(spec)
+        if (T, "cf32") not in arrays:
+            sc = synth.scene_fp32_baseline(SEED, N_STATIONS, N_CHANNELS, T)
+            e = synth.device_voltages(sc, dev)
+            v = torch.empty((sc.n_baselines, N_CHANNELS, T, 4, 2), dtype=torch.float32, device=dev)
+            synth.correlate_torch(e, v, "cf32")
+            del e
+            arrays[(T, "cf32")] = v
+        if (T, fmt) not in arrays:
+            arrays[(T, fmt)] = arrays[(T, "cf32")].to(torch.float16)
+        vis = arrays[(T, fmt)]
+        B = vis.shape[0]
+        params = rfi.rfi_params_default(
+            n_stations=N_STATIONS, n_baselines=B, n_channels=N_CHANNELS, n_samples=T, block_m=M, block_f=F,
+            vis_format=rfi.RFI_VIS_CF16 if fmt == "cf16" else rfi.RFI_VIS_CF32,
+            options=rfi.RFI_OPT_PAPER_MIXED if mixed else 0, sk_d=2.2, sk_low=0.5, sk_high=1.6,
+            ds_gamma=float(min(0.95, np.sqrt(7.815 / (3 * M * F)))))
+        plan = rfi.Plan(params)
+        outs = plan.alloc_outputs(flags=True, stats=False)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup, spec)
+        plan.close()
+        sb = 16 if fmt == "cf16" else 32
+        alg = B * N_CHANNELS * (T * sb + 36) + B * (N_CHANNELS // F) * (T // M)
+        r = {"shape": spec, "samples": T, "kernel_ms_mean": float(per.mean()), "kernel_ms_p50": float(np.median(per)),
+             "achieved_GBs": alg / (per.mean() * 1e-3) / 1e9, "hbm_frac": alg / (per.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out.append(r)
+        progress(f"{spec}: {r['kernel_ms_mean'] * 1e3:.1f} us per launch, {r['hbm_frac']:.3f} of the HBM peak")
+    return out
+
+
 def progress(msg: str) -> None:
     """One line per stage on stderr (stdout carries only the JSON result line)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -525,11 +589,21 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=6.0,
                     help="length of the real-time serving run (0 skips the serving form)")
+    ap.add_argument("--shapes", nargs="+", metavar="FMT:M[xF][m][@T]",
+                    help="time only these window shapes (e.g. cf16:64 cf16:10x2 cf32:10x2m) on the "
+                         "48-station array instead of the benchmark; prints one JSON line of results")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: only --gpus 1 is supported (got {args.gpus}); the screen shards by "
               "baseline with no exchange, and bench.py measures one GPU's share.", file=sys.stderr)
         return 2
+    if args.shapes:
+        from paper_2412_14775_amd import rfi
+        rfi.load_library()
+        res = time_shapes(args.shapes, args.steps, args.warmup)
+        print(json.dumps({"shapes": res, "steps": args.steps, "warmup": args.warmup,
+                          "settle": SETTLE_LOG, "kernel_source_digest": kernel_source_digest()}), flush=True)
+        return 0
 
     scene = synth.scene_fp32_baseline(SEED, N_STATIONS, N_CHANNELS, N_SAMPLES)
     e = synth.make_voltages(scene)                                # [N, C, T, 2] complex64

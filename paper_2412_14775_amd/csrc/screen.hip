@@ -713,8 +713,8 @@ __device__ __forceinline__ void mixed_statistics(const ScreenArgs &a, const floa
 //       raw sum), so every lane reads C samples without tests.  Each lane's load offsets and
 //       tile slots are fixed for the kernel and computed once; the step offset is a scalar.
 //       The channel sums at the end are masked wave sums.
-template <int FMT, int C, int F, bool MIXED, bool PAD>
-__global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
+template <int FMT, int C, int F, bool MIXED, bool PAD, bool PERSIST>
+__global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a, int U) {
   constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
   constexpr int PPS = SB / 16;                  // 16-byte pieces per sample
   constexpr int P = C * PPS;                    // pieces per lane per step (at most, PAD)
@@ -722,11 +722,10 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
   constexpr int CH_SAMPLES = kWave * C / F;     // samples of one channel per step (!PAD)
   static_assert(!(MIXED && PAD), "the paper's mixed precision runs on whole lane groups");
   __shared__ u32x4 tile[kWavesPerBlock][kWave * P];
+  extern __shared__ __align__(16) uint8_t block_flags[];  // PERSIST: U nW bytes
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
-  const int64_t group = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-  const bool active = group < a.n_groups;
   const int S = PAD ? (a.M + C - 1) / C : a.M / C;   // lanes per channel of a window
   const int FS = F * S;                         // lanes that hold samples
   int L = FS;                                   // lanes per window
@@ -737,132 +736,157 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a) {
   const int wps = kWave / L;                    // windows per step
   const int ch_samples = PAD ? wps * a.M : CH_SAMPLES;    // samples of one channel per step
   const int ch_tile = PAD ? wps * S * C * PPS : CH_PIECES; // tile pieces of one channel
+  const int n_steps = (a.nW + wps - 1) / wps;
+  u32x4 *my_tile = tile[wave];
 
-  StreamAcc<1> acc{};                           // this lane's channel: masked sums, kept, moments
-  if (active) {
-    const Thresholds th = stream_thresholds(a, group);
-    const uint8_t *base = a.vis + group * F * (int64_t)a.T * SB;
-    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint8_t *>(base), (short)0, F * a.T * SB, kRsrcWord3);
-    const int n_steps = (a.nW + wps - 1) / wps;
-    u32x4 *my_tile = tile[wave];
-    u32x4 buf[P];
-    // Piece i of a step is piece q = i 64 + lane of the step's F channel runs (channel-major),
-    // q < n_load: its byte offset in the group (the step adds ch_samples SB as a scalar) and,
-    // PAD, its tile slot (otherwise slot q).  Both are fixed for the kernel.  A piece past the
-    // end of a channel (ragged last step) belongs to no valid window: it reads the next channel
-    // of the group, or zeros past the group's buffer (hardware bounds check).
-    int voff[P], slot[PAD ? P : 1];
-    const int n_load = F * ch_samples * PPS;    // !PAD: 64 P
+  // Piece i of a step is piece q = i 64 + lane of the step's F channel runs (channel-major),
+  // q < n_load: its byte offset in the group (the step adds ch_samples SB as a scalar) and,
+  // PAD, its tile slot (otherwise slot q).  Both are fixed for the kernel.  A piece past the
+  // end of a channel (ragged last step) belongs to no valid window: past the group's buffer the
+  // hardware bounds check returns zeros without a memory access; inside it (F > 1, the end of a
+  // channel that is not the last) the last step leaves the piece unread.
+  int voff[P], slot[PAD ? P : 1], tpos[F > 1 ? P : 1];
+  const int n_load = F * ch_samples * PPS;      // !PAD: 64 P
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const int q = i * kWave + lane;
-      voff[i] = 0;
+  for (int i = 0; i < P; ++i) {
+    const int q = i * kWave + lane;
+    voff[i] = 0;
+    if constexpr (F > 1) tpos[i] = 0;
+    if constexpr (PAD) {
+      slot[i] = -1;
+      my_tile[i * kWave + lane] = u32x4{0u, 0u, 0u, 0u};  // the padding stays zero
+    }
+    if (q < n_load) {
+      const int ch = q / (ch_samples * PPS), r = q - ch * ch_samples * PPS;
+      const int t = r / PPS, h = r - t * PPS;  // sample of the channel run, half of it
+      voff[i] = (ch * a.T + t) * SB + h * 16;  // < F T SB < 2^31
+      if constexpr (F > 1) tpos[i] = t;
       if constexpr (PAD) {
-        slot[i] = -1;
-        my_tile[i * kWave + lane] = u32x4{0u, 0u, 0u, 0u};  // the padding stays zero
-      }
-      if (q < n_load) {
-        const int ch = q / (ch_samples * PPS), r = q - ch * ch_samples * PPS;
-        const int t = r / PPS, h = r - t * PPS;  // sample of the channel run, half of it
-        voff[i] = (ch * a.T + t) * SB + h * 16;  // < F T SB < 2^31
-        if constexpr (PAD) {
-          const int w = t / a.M, o = t - w * a.M;  // window of the step, sample of the window
-          slot[i] = ch * ch_tile + (w * S * C + o) * PPS + h;
-        }
+        const int w = t / a.M, o = t - w * a.M;  // window of the step, sample of the window
+        slot[i] = ch * ch_tile + (w * S * C + o) * PPS + h;
       }
     }
-    auto issue = [&](int step) {
-      const int soff = step * ch_samples * SB;
+  }
+  const int my_piece = act ? f * ch_tile + (j * S * C + s * C) * PPS : 0;
+
+  // PERSIST: block b screens the channel groups [b U, (b + 1) U) (its waves take every fourth)
+  // and keeps their flags in LDS until the last is done, then writes them in one pass
+  const int64_t first = PERSIST ? (int64_t)blockIdx.x * U : 0;
+  const int64_t last = PERSIST ? min(first + (int64_t)U, a.n_groups) : 0;
+  for (int64_t group = PERSIST ? first + wave : (int64_t)blockIdx.x * kWavesPerBlock + wave;;
+       group += kWavesPerBlock) {
+    const bool active = group < (PERSIST ? last : a.n_groups);
+    if (PERSIST && !active) break;
+    StreamAcc<1> acc{};                         // this lane's channel: masked sums, kept, moments
+    if (active) {
+      const Thresholds th = stream_thresholds(a, group);
+      const uint8_t *base = a.vis + group * F * (int64_t)a.T * SB;
+      const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<uint8_t *>(base), (short)0, F * a.T * SB, kRsrcWord3);
+      u32x4 buf[P] = {};                        // a piece the last step leaves unread keeps its old value
+      auto issue = [&](int step) {
+        const int soff = step * ch_samples * SB;
+        const int room = step == n_steps - 1 ? a.T - step * ch_samples : ch_samples;  // uniform
 #pragma unroll
-      for (int i = 0; i < P; ++i)
-        if (!PAD || slot[i] >= 0)
-          buf[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i], soff, kLoadStreaming));
-    };
-    const int my_piece = act ? f * ch_tile + (j * S * C + s * C) * PPS : 0;
-    issue(0);
-    for (int step = 0; step < n_steps; ++step) {
-      wave_lds_order();
+        for (int i = 0; i < P; ++i)
+          if ((!PAD || slot[i] >= 0) && (F == 1 || tpos[i] < room))
+            buf[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i], soff, kLoadStreaming));
+      };
+      issue(0);
+      for (int step = 0; step < n_steps; ++step) {
+        wave_lds_order();
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        if constexpr (PAD) {
-          if (slot[i] >= 0) my_tile[slot[i]] = buf[i];
+        for (int i = 0; i < P; ++i) {
+          if constexpr (PAD) {
+            if (slot[i] >= 0) my_tile[slot[i]] = buf[i];
+          } else {
+            my_tile[i * kWave + lane] = buf[i];
+          }
+        }
+        wave_lds_order();
+        if (step + 1 < n_steps) issue(step + 1);
+        float ws[8] = {}, wr[8] = {};
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+          if (!act) break;                      // PAD: a lane left over in its group
+          if constexpr (FMT == FMT_CF32) {
+            const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k]);
+            const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k + 1]);
+            const float x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            if constexpr (MIXED)
+              accumulate_sample_mixed(ws, wr, x, a.eps);
+            else
+              accumulate_sample(ws, wr, x, a.eps);
+          } else {
+            static_assert(!MIXED, "the paper's mixed precision takes complex64 input");
+            accumulate_sample_h(ws, wr, my_tile[my_piece + k], a.eps);
+          }
+        }
+        group_sum8_rt<MIXED ? 2 : 8>(ws, L);   // ws now holds the window totals
+        const int w = step * wps + j;
+        const bool valid = w < a.nW;
+        // one lane per window plays the leader of finish_window (kept count, moments, flag and
+        // statistics); every lane folds its own raw partial into its own channel's sum
+        const float wr1[1][8] = {{wr[0], wr[1], wr[2], wr[3], wr[4], wr[5], wr[6], wr[7]}};
+        if constexpr (MIXED) {
+          Thresholds t16{round16(th.s_low), round16(th.s_high), round16(th.g_re), round16(th.g_im)};
+          finish_window<1, true>(a, t16, ws, wr1, group * a.nW + w, valid, g == 0, acc,
+                                 PERSIST ? block_flags : nullptr, first * a.nW);
         } else {
-          my_tile[i * kWave + lane] = buf[i];
+          finish_window<1>(a, th, ws, wr1, group * a.nW + w, valid, g == 0, acc,
+                           PERSIST ? block_flags : nullptr, first * a.nW);
         }
       }
-      wave_lds_order();
-      if (step + 1 < n_steps) issue(step + 1);
-      float ws[8] = {}, wr[8] = {};
+    }
+    // masked sums: reduce over the lanes of each channel
+    float chan[PAD ? F : 1][8];
+    if constexpr (PAD) {                        // channel bits are not lane bits: masked wave sums
 #pragma unroll
-      for (int k = 0; k < C; ++k) {
-        if (!act) break;                        // PAD: a lane left over in its group
-        if constexpr (FMT == FMT_CF32) {
-          const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k]);
-          const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k + 1]);
-          const float x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-          if constexpr (MIXED)
-            accumulate_sample_mixed(ws, wr, x, a.eps);
-          else
-            accumulate_sample(ws, wr, x, a.eps);
-        } else {
-          static_assert(!MIXED, "the paper's mixed precision takes complex64 input");
-          accumulate_sample_h(ws, wr, my_tile[my_piece + k], a.eps);
-        }
-      }
-      group_sum8_rt<MIXED ? 2 : 8>(ws, L);     // ws now holds the window totals
-      const int w = step * wps + j;
-      const bool valid = w < a.nW;
-      // one lane per window plays the leader of finish_window (kept count, moments, flag and
-      // statistics); every lane folds its own raw partial into its own channel's sum
-      const float wr1[1][8] = {{wr[0], wr[1], wr[2], wr[3], wr[4], wr[5], wr[6], wr[7]}};
-      if constexpr (MIXED) {
-        Thresholds t16{round16(th.s_low), round16(th.s_high), round16(th.g_re), round16(th.g_im)};
-        finish_window<1, true>(a, t16, ws, wr1, group * a.nW + w, valid, g == 0, acc);
-      } else {
-        finish_window<1>(a, th, ws, wr1, group * a.nW + w, valid, g == 0, acc);
+      for (int c = 0; c < F; ++c)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) chan[c][e] = group_sum<64>(act && f == c ? acc.sum[0][e] : 0.0f);
+    } else {                                    // skip the f bits of the lane index
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float v = acc.sum[0][e];
+        for (int m = 1; m < kWave; m <<= 1)
+          if (m < S || m >= L) v += __shfl_xor(v, m);
+        chan[0][e] = v;
       }
     }
+    const float kept = group_sum<64>(acc.kept);
+    Moments mom = acc.mom;
+    if (a.state != nullptr) {
+#pragma unroll
+      for (int m = 1; m < kWave; m <<= 1) mom = moments_merge(mom, moments_shfl_xor(mom, m));
+    }
+    if (active) {
+      const float inv = kept > 0.0f ? 1.0f / kept : 0.0f;
+      auto write_channel = [&](int c, const float v[8]) {
+        const int64_t stream = group * F + c;
+        f32x4 *out = reinterpret_cast<f32x4 *>(a.avg + stream * 8);
+        out[0] = f32x4{v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv};
+        out[1] = f32x4{v[4] * inv, v[5] * inv, v[6] * inv, v[7] * inv};
+        a.weight[stream] = kept * a.invT;
+      };
+      if constexpr (PAD) {
+        if (lane == 0)
+#pragma unroll
+          for (int c = 0; c < F; ++c) write_channel(c, chan[c]);
+      } else if (lane < L && s == 0) {          // lane f S of window 0 writes channel f
+        write_channel(f, chan[0]);
+      }
+      if (lane == 0 && a.state != nullptr && mom.n > 0u) state_merge(a.state + group, mom);
+    }
+    if (!PERSIST) break;
   }
-  // masked sums: reduce over the lanes of each channel
-  float chan[PAD ? F : 1][8];
-  if constexpr (PAD) {                          // channel bits are not lane bits: masked wave sums
-#pragma unroll
-    for (int c = 0; c < F; ++c)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) chan[c][e] = group_sum<64>(act && f == c ? acc.sum[0][e] : 0.0f);
-  } else {                                      // skip the f bits of the lane index
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      float v = acc.sum[0][e];
-      for (int m = 1; m < kWave; m <<= 1)
-        if (m < S || m >= L) v += __shfl_xor(v, m);
-      chan[0][e] = v;
+  if constexpr (PERSIST) {
+    __syncthreads();
+    if (a.flags != nullptr) {
+      const int64_t base = first * a.nW, n = (last - first) * a.nW;
+      for (int64_t i = threadIdx.x; i < n; i += kBlock) a.flags[base + i] = block_flags[i];
     }
   }
-  const float kept = group_sum<64>(acc.kept);
-  Moments mom = acc.mom;
-  if (a.state != nullptr) {
-#pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) mom = moments_merge(mom, moments_shfl_xor(mom, m));
-  }
-  if (!active) return;
-  const float inv = kept > 0.0f ? 1.0f / kept : 0.0f;
-  auto write_channel = [&](int c, const float v[8]) {
-    const int64_t stream = group * F + c;
-    f32x4 *out = reinterpret_cast<f32x4 *>(a.avg + stream * 8);
-    out[0] = f32x4{v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv};
-    out[1] = f32x4{v[4] * inv, v[5] * inv, v[6] * inv, v[7] * inv};
-    a.weight[stream] = kept * a.invT;
-  };
-  if constexpr (PAD) {
-    if (lane == 0)
-#pragma unroll
-      for (int c = 0; c < F; ++c) write_channel(c, chan[c]);
-  } else if (lane < L && s == 0) {              // lane f S of window 0 writes channel f
-    write_channel(f, chan[0]);
-  }
-  if (lane == 0 && a.state != nullptr && mom.n > 0u) state_merge(a.state + group, mom);
 }
 
 // s += b with the running compensation c (Kahan): the error of a long sum of
@@ -1030,23 +1054,45 @@ hipError_t launch_generic(const ScreenArgs &a, hipStream_t stream) {
 
 constexpr int kFourBlocksLds = 33024;  // LDS per block that leaves room for four (160 KiB / 5 < this)
 
+template <int FMT, int C, bool MIXED, bool PAD, bool PERSIST>
+hipError_t launch_windows_f(dim3 grid, unsigned lds, int U, const ScreenArgs &a, hipStream_t stream) {
+  switch (a.F) {
+    case 1: hipLaunchKernelGGL((screen_windows<FMT, C, 1, MIXED, PAD, PERSIST>), grid, dim3(kBlock), lds, stream, a, U); break;
+    case 2: hipLaunchKernelGGL((screen_windows<FMT, C, 2, MIXED, PAD, PERSIST>), grid, dim3(kBlock), lds, stream, a, U); break;
+    case 4: hipLaunchKernelGGL((screen_windows<FMT, C, 4, MIXED, PAD, PERSIST>), grid, dim3(kBlock), lds, stream, a, U); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int FMT, int C, bool MIXED, bool PAD>
 hipError_t launch_windows_k(const ScreenArgs &a, hipStream_t stream) {
-  const int64_t blocks = (a.n_groups + kWavesPerBlock - 1) / kWavesPerBlock;
-  const dim3 grid((unsigned)blocks), block(kBlock);
   // exact complex-half layouts of 5 or more samples per lane: at most four blocks per CU (unused
   // dynamic LDS past 160 KiB / 5): 1-2 % faster than the five their registers allow (10 x 2, 5 x 4,
   // M = 20, 48); padded layouts and runs of 3 are not
   constexpr int tile_bytes = kWavesPerBlock * kWave * C * (FMT == FMT_CF32 ? 2 : 1) * 16;
   constexpr unsigned pad = FMT == FMT_CF16 && !PAD && !MIXED && C >= 5 && tile_bytes < kFourBlocksLds
                                ? (unsigned)(kFourBlocksLds - tile_bytes) : 0u;
-  switch (a.F) {
-    case 1: hipLaunchKernelGGL((screen_windows<FMT, C, 1, MIXED, PAD>), grid, block, pad, stream, a); break;
-    case 2: hipLaunchKernelGGL((screen_windows<FMT, C, 2, MIXED, PAD>), grid, block, pad, stream, a); break;
-    case 4: hipLaunchKernelGGL((screen_windows<FMT, C, 4, MIXED, PAD>), grid, block, pad, stream, a); break;
-    default: return hipErrorInvalidValue;
+  // complex64 exact layouts of at most 6 samples per lane (the paper's mixed form included) with
+  // a flag array run persistent: each block screens a range of channel groups and writes their
+  // flags, held in LDS, once they are done, at the most blocks per CU (4, 3, 2) whose flag range
+  // fits beside the tile (two for runs of 5: 10 x 2 +5.5 %, 5 x 4 +5.1 %, M = 20 +4.5 %, the mixed
+  // form +3.4 %; M = 48 +1.1 %; runs of 8, 16 x 2, -3.1 %).  Complex half gains nothing that way
+  // (10 x 2 +0 %, 5 x 4 +1.4 %, M = 20 -1.4 %) and padded layouts lose 2-6 %: one wave per group.
+  if constexpr (FMT == FMT_CF32 && !PAD && C <= 6) {
+    for (int bpc = 4; bpc >= 2 && a.flags != nullptr && a.n_cu > 0; --bpc) {
+      const int64_t G = (int64_t)a.n_cu * bpc;
+      const int64_t U = (a.n_groups + G - 1) / G;
+      const int64_t room = 163840 / bpc - 512 - tile_bytes;
+      if (U * a.nW <= room) {
+        const int64_t blocks = (a.n_groups + U - 1) / U;
+        const unsigned lds = (unsigned)std::max<int64_t>(U * a.nW, (int64_t)pad);
+        return launch_windows_f<FMT, C, MIXED, PAD, true>(dim3((unsigned)blocks), lds, (int)U, a, stream);
+      }
+    }
   }
-  return hipGetLastError();
+  const int64_t blocks = (a.n_groups + kWavesPerBlock - 1) / kWavesPerBlock;
+  return launch_windows_f<FMT, C, MIXED, PAD, false>(dim3((unsigned)blocks), pad, 0, a, stream);
 }
 
 // PAD (padded runs or partial lane groups) exists only outside the paper's mixed precision.
