@@ -170,31 +170,43 @@ __device__ __forceinline__ void state_merge(StateRec *st, const Moments &b) {
   *st = r;
 }
 
+// x into the running sum s; FIRST: s is still empty and takes x itself (the same value as
+// 0 + x, without the zero)
+template <bool FIRST>
+__device__ __forceinline__ void add_to(float &s, float x) {
+  if constexpr (FIRST)
+    s = x;
+  else
+    s += x;
+}
+
 // Per-sample terms of Tables 1 and 2 from one sample's Stokes parameters (eq. IQUV),
 // added to the window sums ws = (S1, S2, sum q^, u^, v^ of Re, of Im).
+template <bool FIRST = false>
 __device__ __forceinline__ void accumulate_stokes(float ws[8], float Ir, float Ii, float Qr, float Qi,
                                                   float Ur, float Ui, float Vr, float Vi, float eps) {
   const float y = Ir * Ir + Ii * Ii;
-  ws[0] += hw_sqrt(y);
-  ws[1] += y;
+  add_to<FIRST>(ws[0], hw_sqrt(y));
+  add_to<FIRST>(ws[1], y);
   const float rr = hw_rcp(hw_sqrt(Qr * Qr + Ur * Ur + Vr * Vr) + eps);
-  ws[2] += Qr * rr;
-  ws[3] += Ur * rr;
-  ws[4] += Vr * rr;
+  add_to<FIRST>(ws[2], Qr * rr);
+  add_to<FIRST>(ws[3], Ur * rr);
+  add_to<FIRST>(ws[4], Vr * rr);
   const float ri = hw_rcp(hw_sqrt(Qi * Qi + Ui * Ui + Vi * Vi) + eps);
-  ws[5] += Qi * ri;
-  ws[6] += Ui * ri;
-  ws[7] += Vi * ri;
+  add_to<FIRST>(ws[5], Qi * ri);
+  add_to<FIRST>(ws[6], Ui * ri);
+  add_to<FIRST>(ws[7], Vi * ri);
 }
 
 // One sample: Stokes parameters and the per-sample terms into ws, the sample itself
 // into the raw sums wr.  x = (xx_re, xx_im, xy_re, xy_im, yx_re, yx_im, yy_re, yy_im).
+template <bool FIRST = false>
 __device__ __forceinline__ void accumulate_sample(float ws[8], float wr[8], const float x[8],
                                                   float eps) {
-  accumulate_stokes(ws, x[0] + x[6], x[1] + x[7], x[0] - x[6], x[1] - x[7], x[2] + x[4], x[3] + x[5],
-                    x[5] - x[3], x[2] - x[4], eps);  // I, Q, U, V = j (xy - yx)
+  accumulate_stokes<FIRST>(ws, x[0] + x[6], x[1] + x[7], x[0] - x[6], x[1] - x[7], x[2] + x[4], x[3] + x[5],
+                           x[5] - x[3], x[2] - x[4], eps);  // I, Q, U, V = j (xy - yx)
 #pragma unroll
-  for (int k = 0; k < 8; ++k) wr[k] += x[k];
+  for (int k = 0; k < 8; ++k) add_to<FIRST>(wr[k], x[k]);
 }
 
 // Sums and differences of binary16 halves of 32-bit words (half 0 = the low one) in
@@ -217,22 +229,36 @@ __device__ __forceinline__ float mix_acc(float acc, uint32_t a) {  // acc + a_SA
   asm("v_fma_mix_f32 %0, %1, 1.0, %0 op_sel:[%2,0,0] op_sel_hi:[1,0,0]" : "+v"(acc) : "v"(a), "n"(SA));
   return acc;
 }
+template <int SA>
+__device__ __forceinline__ float mix_cvt(uint32_t a) {  // a_SA (0 + a_SA)
+  float d;
+  asm("v_fma_mix_f32 %0, %1, 1.0, 0 op_sel:[%2,0,0] op_sel_hi:[1,0,0]" : "=v"(d) : "v"(a), "n"(SA));
+  return d;
+}
+template <bool FIRST, int SA>
+__device__ __forceinline__ void mix_add_to(float &s, uint32_t a) {
+  if constexpr (FIRST)
+    s = mix_cvt<SA>(a);
+  else
+    s = mix_acc<SA>(s, a);
+}
 
 // accumulate_sample for a complex-half sample as it sits in memory (words xx, xy, yx,
 // yy; real part in the low half), without separate conversions: the same float32
 // results bit for bit, with 8 fewer VALU operations per sample.
+template <bool FIRST = false>
 __device__ __forceinline__ void accumulate_sample_h(float ws[8], float wr[8], u32x4 h, float eps) {
-  accumulate_stokes(ws, mix_add<0, 0>(h.x, h.w), mix_add<1, 1>(h.x, h.w), mix_sub<0, 0>(h.x, h.w),
-                    mix_sub<1, 1>(h.x, h.w), mix_add<0, 0>(h.y, h.z), mix_add<1, 1>(h.y, h.z),
-                    mix_sub<1, 1>(h.z, h.y), mix_sub<0, 0>(h.y, h.z), eps);
-  wr[0] = mix_acc<0>(wr[0], h.x);
-  wr[1] = mix_acc<1>(wr[1], h.x);
-  wr[2] = mix_acc<0>(wr[2], h.y);
-  wr[3] = mix_acc<1>(wr[3], h.y);
-  wr[4] = mix_acc<0>(wr[4], h.z);
-  wr[5] = mix_acc<1>(wr[5], h.z);
-  wr[6] = mix_acc<0>(wr[6], h.w);
-  wr[7] = mix_acc<1>(wr[7], h.w);
+  accumulate_stokes<FIRST>(ws, mix_add<0, 0>(h.x, h.w), mix_add<1, 1>(h.x, h.w), mix_sub<0, 0>(h.x, h.w),
+                           mix_sub<1, 1>(h.x, h.w), mix_add<0, 0>(h.y, h.z), mix_add<1, 1>(h.y, h.z),
+                           mix_sub<1, 1>(h.z, h.y), mix_sub<0, 0>(h.y, h.z), eps);
+  mix_add_to<FIRST, 0>(wr[0], h.x);
+  mix_add_to<FIRST, 1>(wr[1], h.x);
+  mix_add_to<FIRST, 0>(wr[2], h.y);
+  mix_add_to<FIRST, 1>(wr[3], h.y);
+  mix_add_to<FIRST, 0>(wr[4], h.z);
+  mix_add_to<FIRST, 1>(wr[5], h.z);
+  mix_add_to<FIRST, 0>(wr[6], h.w);
+  mix_add_to<FIRST, 1>(wr[7], h.w);
 }
 
 // Per-stream running results of a wave.  A window covers F adjacent channels
@@ -815,11 +841,16 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a, int
             const float x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
             if constexpr (MIXED)
               accumulate_sample_mixed(ws, wr, x, a.eps);
+            else if (!PAD && k == 0)            // every lane holds C samples: the first starts the sums
+              accumulate_sample<true>(ws, wr, x, a.eps);
             else
               accumulate_sample(ws, wr, x, a.eps);
           } else {
             static_assert(!MIXED, "the paper's mixed precision takes complex64 input");
-            accumulate_sample_h(ws, wr, my_tile[my_piece + k], a.eps);
+            if (!PAD && k == 0)
+              accumulate_sample_h<true>(ws, wr, my_tile[my_piece + k], a.eps);
+            else
+              accumulate_sample_h(ws, wr, my_tile[my_piece + k], a.eps);
           }
         }
         group_sum8_rt<MIXED ? 2 : 8>(ws, L);   // ws now holds the window totals
@@ -978,14 +1009,25 @@ constexpr unsigned kTiledCf16Pad[kMaxTiledLog2M + 1] = {0u, 0u, 7680u, 22528u, 2
 // segment per stream: +1 % at M = 64, +4 % at M = 16.  Complex half lost 1-4 % in this form
 // (more registers per loop) and keeps the one-stream-per-wave launch.
 constexpr int kPersistBlocksPerCu = 3;
+
 constexpr int64_t kPersistFlagBytes = 19456;
+
+// Groups per block of a persistent launch of at most G blocks: ceil(n / G), rounded up to a
+// multiple of the waves per block once that exceeds them, so that every wave of every block
+// but the last screens the same number of groups and the waves end together (37 groups per
+// block leave one wave in four a tenth group after the others).
+inline int64_t balanced_share(int64_t n, int64_t G) {
+  int64_t U = (n + G - 1) / G;
+  if (U > kWavesPerBlock) U = (U + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
+  return U;
+}
 
 template <int FMT, int LOG2M>
 hipError_t launch_tiled(const ScreenArgs &a, hipStream_t stream) {
   if constexpr (FMT == FMT_CF32) {
     if (a.n_seg == 1 && a.flags != nullptr && a.n_cu > 0) {
       const int64_t G = (int64_t)a.n_cu * kPersistBlocksPerCu;
-      const int64_t U = (a.n_groups + G - 1) / G;
+      const int64_t U = balanced_share(a.n_groups, G);
       if (U * a.nW <= kPersistFlagBytes) {
         const int64_t blocks = (a.n_groups + U - 1) / U;
         const unsigned lds = (unsigned)std::max<int64_t>(U * a.nW, kCf32OccupancyPad);
@@ -1082,7 +1124,7 @@ hipError_t launch_windows_k(const ScreenArgs &a, hipStream_t stream) {
   if constexpr (FMT == FMT_CF32 && !PAD && C <= 6) {
     for (int bpc = 4; bpc >= 2 && a.flags != nullptr && a.n_cu > 0; --bpc) {
       const int64_t G = (int64_t)a.n_cu * bpc;
-      const int64_t U = (a.n_groups + G - 1) / G;
+      const int64_t U = balanced_share(a.n_groups, G);
       const int64_t room = 163840 / bpc - 512 - tile_bytes;
       if (U * a.nW <= room) {
         const int64_t blocks = (a.n_groups + U - 1) / U;

@@ -355,10 +355,11 @@ def test_size_checks_in_binding():
 
 
 def test_persistent_launch_with_a_ragged_last_block():
-    """The persistent complex64 launch gives each block U = ceil(streams / (3 x CUs)) streams: 48
-    stations x 33 channels (38 808 streams) x 256 samples at M = 16 on 256 CUs makes U = 51 and
-    a last block of 48 streams.  Every stream, the last block's included, against the oracle;
-    flags against the rule applied to the kernel's own statistics."""
+    """The persistent complex64 launch gives each block U = ceil(streams / (3 x CUs)) streams,
+    rounded up to a multiple of its 4 waves: 48 stations x 33 channels (38 808 streams) x 256
+    samples at M = 16 on 256 CUs makes U = 52 and a last block of 16 streams (4 per wave).  Every
+    stream, the last block's included, against the oracle; flags against the rule applied to the
+    kernel's own statistics."""
     import torch
     from paper_2412_14775_amd import rfi
     N, C, T, M = 48, 33, 256, 16
@@ -367,10 +368,12 @@ def test_persistent_launch_with_a_ragged_last_block():
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     G = 3 * n_cu
     U = -(-B * C // G)
+    if U > 4:
+        U = -(-U // 4) * 4
     last = B * C - (-(-B * C // U) - 1) * U
     print(f"{n_cu} CUs: U = {U} streams per block, last block {last}")
     if n_cu == 256:
-        assert (U, last) == (51, 48)
+        assert (U, last) == (52, 16)
     op, gpu = screen_both(vis, M, **thresholds_for(M))
     rep = compare(gpu, vis, op, TOL_F32, label="persistent ragged")
     assert 0.0 < rep["flagged_frac"] < 0.5
