@@ -106,9 +106,10 @@ void rfi_params_default(rfi_params *p);
  * the plan's device state on `device` (the ADAPTIVE state, zeroed; nothing
  * otherwise).  On success *out receives the plan; on error *out is NULL.
  * Every M >= 2 and F in {1, 2, 4} is screened; the kernel depends on the shape: M a
- * power of two <= 4096 (F = 1); M = K S with K <= 8 and F S <= 64; M of more than 64
- * (complex64) / 128 (complex half) samples (F = 1); anything else one lane per window
- * (correct, slower).
+ * power of two <= 4096 (F = 1); windows cut into F ceil(M / C) <= 64 runs of C <= 8
+ * samples, one per lane; M of more than 128 (complex64) / 256 (complex half) samples
+ * (F = 1); wider time x frequency windows (F > 1) over several steps of one channel's
+ * chunk each.
  * Errors: INVALID_ARGUMENT (shape or threshold rules above), UNSUPPORTED (block_f not
  * 1, 2 or 4; RFI_OPT_PAPER_MIXED outside its shapes), DEVICE, OUT_OF_MEMORY.
  */

@@ -6,8 +6,9 @@
 //   screen_windows  windows of M = K S samples x F channels (non-power-of-two M and
 //                   the paper's time x frequency windows), optionally in the
 //                   paper's mixed precision (Tables 3-4);
-//   screen_long     time-only windows of more than a quarter of a step, edges anywhere;
-//   screen_generic  any other shape, one lane per window.
+//   screen_long     time-only windows of more than half a step, edges anywhere;
+//   screen_wide     time x frequency windows wider than 64 lanes of runs of 8 samples,
+//                   a window over several steps.
 //
 // screen_tiled, one pass over the visibilities, bound by HBM bandwidth:
 //   * each wave owns one stream (baseline, channel) or a window-aligned segment
@@ -920,28 +921,27 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a, int
   }
 }
 
-// s += b with the running compensation c (Kahan): the error of a long sum of
-// block sums stays at a few ulps whatever the number of blocks.
-__device__ __forceinline__ void compensated_add(float &s, float &c, float b) {
-  const float y = b - c;
-  const float t = s + y;
-  c = (t - s) - y;
-  s = t;
-}
-
-constexpr int kGenericBlock = 64;  // samples summed plainly before a compensated add
-
-// Any window length (M >= 2, including M that is not a power of two) and
-// time x frequency windows of F = 1, 2 or 4 adjacent channels: one wave per
-// channel group, one lane per window, samples read directly.  Slower than the
-// tiled kernel; used for the shapes the tiled kernel does not cover.  A lane
-// sums its window alone, so the sums run in blocks of 64 samples (as long as
-// the sequential runs of the other kernels) folded in with compensation: the
-// rounding error does not grow with M.
-template <int FMT, int F>
-__global__ void __launch_bounds__(kBlock) screen_generic(const ScreenArgs a) {
+// Time x frequency windows wider than one lane group (F > 1 and F ceil(M / 8) > 64 runs): one
+// wave per channel group.  A step is one chunk of one channel's run of a window, up to 64 C
+// consecutive samples (C per lane), so a run of M samples takes R = ceil(M / (64 C)) steps and a
+// window F R.  The chunk is loaded coalesced and transposed through the wave's LDS tile as in
+// the tiled kernel; each step's buffer resource ends where the run does, so in the last chunk
+// of a run the loads past its end return zeros with no memory access (a zero sample adds exactly
+// zero to every window and raw sum).  A lane sums its C samples of a step, then adds those step
+// sums into the window sums and into its channel's raw sums: no lane sums more than C + F R
+// terms in a row.  After the window's last step: one wave reduction and the window finish.
+template <int FMT, int C, int F>
+__global__ void __launch_bounds__(kBlock) screen_wide(const ScreenArgs a) {
   constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
+  constexpr int PPS = SB / 16;                  // 16-byte pieces per sample
+  constexpr int P = C * PPS;                    // pieces per lane per step
+  constexpr int CHUNK = kWave * C;              // samples per step
+  static_assert(F == 2 || F == 4, "wide windows span 2 or 4 channels");
+  __shared__ u32x4 tile[kWavesPerBlock][kWave * P];
   __shared__ float xfer[kWavesPerBlock][kXfer];
+  // eight pieces per lane: the tiled kernel's bank-conflict-free slots
+  auto slot = [](int q) { return P == kPieces ? lds_slot(q) : q; };
+
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
   const int64_t group = (int64_t)blockIdx.x * kWavesPerBlock + wave;
@@ -949,40 +949,74 @@ __global__ void __launch_bounds__(kBlock) screen_generic(const ScreenArgs a) {
   StreamAcc<F> acc{};
   if (active) {
     const Thresholds th = stream_thresholds(a, group);
-    const uint8_t *base = a.vis + group * F * (int64_t)a.T * SB;
-    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint8_t *>(base), (short)0, F * a.T * SB, kRsrcWord3);
-    for (int w = lane; w < a.nW; w += kWave) {
-      float ws[8] = {}, wr[F][8] = {}, cs[8] = {};
+    const uint8_t *gbase = a.vis + group * F * (int64_t)a.T * SB;
+    const int R = (a.M + CHUNK - 1) / CHUNK;   // chunks per channel run
+    u32x4 *my_tile = tile[wave];
+    u32x4 buf[P];
+    int lj = 0, lf = 0, lc = 0;                 // the next chunk to load: window, channel, chunk
+    auto issue = [&]() {
+      const int64_t start = (int64_t)lf * a.T + (int64_t)lj * a.M + (int64_t)lc * CHUNK;  // sample of the group
+      const int len = min(CHUNK, a.M - lc * CHUNK);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<uint8_t *>(gbase + start * SB), (short)0, len * SB, kRsrcWord3);
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        buf[i] = __builtin_bit_cast(
+            u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (unsigned)((i * kWave + lane) * 16), 0, kLoadStreaming));
+      if (++lc == R) {
+        lc = 0;
+        if (++lf == F) {
+          lf = 0;
+          ++lj;
+        }
+      }
+    };
+    float ws[8] = {}, wr[F][8] = {};
+    issue();
+    for (int j = 0; j < a.nW; ++j) {
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        float cr[8] = {};
-        for (int t0 = 0; t0 < a.M; t0 += kGenericBlock) {
-          const int t1 = min(a.M, t0 + kGenericBlock);
-          float bs[8] = {}, br[8] = {};
-          for (int t = t0; t < t1; ++t) {
-            const unsigned off = (unsigned)(f * a.T + w * a.M + t) * SB;
-            float x[8];
-            if constexpr (FMT == FMT_CF32) {
-              const f32x4 lo = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
-              const f32x4 hi = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + 16, 0, kLoadStreaming));
-              x[0] = lo[0]; x[1] = lo[1]; x[2] = lo[2]; x[3] = lo[3];
-              x[4] = hi[0]; x[5] = hi[1]; x[6] = hi[2]; x[7] = hi[3];
-            } else {
-              const f16x8 h = __builtin_bit_cast(f16x8, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, kLoadStreaming));
+        for (int c = 0; c < R; ++c) {
+          wave_lds_order();
 #pragma unroll
-              for (int k = 0; k < 8; ++k) x[k] = (float)h[k];
+          for (int i = 0; i < P; ++i) my_tile[slot(i * kWave + lane)] = buf[i];
+          wave_lds_order();
+          if (lj < a.nW) issue();
+          float ps[8], pr[8];
+#pragma unroll
+          for (int k = 0; k < C; ++k) {
+            if constexpr (FMT == FMT_CF32) {
+              const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[slot(P * lane + 2 * k)]);
+              const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[slot(P * lane + 2 * k + 1)]);
+              const float x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+              if (k == 0)
+                accumulate_sample<true>(ps, pr, x, a.eps);
+              else
+                accumulate_sample(ps, pr, x, a.eps);
+            } else {
+              if (k == 0)
+                accumulate_sample_h<true>(ps, pr, my_tile[slot(P * lane + k)], a.eps);
+              else
+                accumulate_sample_h(ps, pr, my_tile[slot(P * lane + k)], a.eps);
             }
-            accumulate_sample(bs, br, x, a.eps);
           }
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            compensated_add(ws[k], cs[k], bs[k]);
-            compensated_add(wr[f][k], cr[k], br[k]);
+            ws[k] += ps[k];
+            wr[f][k] += pr[k];
           }
         }
       }
-      finish_window<F>(a, th, ws, wr, group * a.nW + w, true, true, acc);
+      float tot[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) tot[k] = group_sum<kWave>(ws[k]);
+      finish_window<F>(a, th, tot, wr, group * a.nW + j, true, lane == 0, acc);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        ws[k] = 0.0f;
+#pragma unroll
+        for (int f = 0; f < F; ++f) wr[f][k] = 0.0f;
+      }
     }
   }
   finish_stream<F>(a, acc, group, 0, active, wave, lane, xfer);
@@ -1081,17 +1115,37 @@ hipError_t launch_long(const ScreenArgs &a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int FMT>
-hipError_t launch_generic(const ScreenArgs &a, hipStream_t stream) {
+template <int FMT, int C>
+hipError_t launch_wide_c(const ScreenArgs &a, hipStream_t stream) {
   const int64_t blocks = (a.n_groups + kWavesPerBlock - 1) / kWavesPerBlock;
   const dim3 grid((unsigned)blocks), block(kBlock);
   switch (a.F) {
-    case 1: hipLaunchKernelGGL((screen_generic<FMT, 1>), grid, block, 0, stream, a); break;
-    case 2: hipLaunchKernelGGL((screen_generic<FMT, 2>), grid, block, 0, stream, a); break;
-    case 4: hipLaunchKernelGGL((screen_generic<FMT, 4>), grid, block, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((screen_wide<FMT, C, 2>), grid, block, 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((screen_wide<FMT, C, 4>), grid, block, 0, stream, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int FMT>
+hipError_t launch_wide(const ScreenArgs &a, hipStream_t stream) {
+  if constexpr (FMT == FMT_CF32) {
+    switch (wide_chunk(a.M, FMT)) {
+      case 2: return launch_wide_c<FMT, 2>(a, stream);
+      case 3: return launch_wide_c<FMT, 3>(a, stream);
+      case 4: return launch_wide_c<FMT, 4>(a, stream);
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (wide_chunk(a.M, FMT)) {
+      case 4: return launch_wide_c<FMT, 4>(a, stream);
+      case 5: return launch_wide_c<FMT, 5>(a, stream);
+      case 6: return launch_wide_c<FMT, 6>(a, stream);
+      case 7: return launch_wide_c<FMT, 7>(a, stream);
+      case 8: return launch_wide_c<FMT, 8>(a, stream);
+      default: return hipErrorInvalidValue;
+    }
+  }
 }
 
 constexpr int kFourBlocksLds = 33024;  // LDS per block that leaves room for four (160 KiB / 5 < this)
@@ -1213,6 +1267,24 @@ bool tiled_supports(int M) {
   return l >= 1 && l <= kMaxTiledLog2M;
 }
 
+// Samples per lane of the wide-window kernel: the C (complex half 4-8, complex64 2-4: at most
+// eight 16-byte pieces per lane) whose chunks of 64 C samples fill the largest share of their
+// lane slots over a run of M samples, M / (ceil(M / 64 C) 64 C); ties to the larger C.
+int wide_chunk(int M, int fmt) {
+  const int lo = fmt == FMT_CF32 ? 2 : 4, hi = fmt == FMT_CF32 ? 4 : 8;
+  int best = hi;
+  double best_share = 0.0;
+  for (int C = hi; C >= lo; --C) {
+    const int64_t chunk = (int64_t)kWave * C, slots = (M + chunk - 1) / chunk * chunk;
+    const double share = (double)M / (double)slots;
+    if (share > best_share + 1e-12) {
+      best = C;
+      best_share = share;
+    }
+  }
+  return best;
+}
+
 WindowsLayout windows_layout(int M, int F, int fmt, bool mixed) {
   // Runs of C = 2..8 samples per lane, S = ceil(M / C) runs per channel, F S <= 64 lanes
   // rounded up to a power of two L: the layout that fills the largest share M F / (L C) of
@@ -1243,7 +1315,7 @@ KernelKind kernel_for(int M, int F, int fmt, bool mixed) {
   const bool long_ok = F == 1 && 2 * M > kWave * (fmt == FMT_CF32 ? 4 : 8);
   if (w.C > 0 && (!w.pad || !long_ok || w.share >= kPadOverLong)) return kWindows;
   if (long_ok) return kLong;
-  return kGeneric;
+  return F > 1 ? kWide : kNone;  // every F = 1 length has one of the kernels above
 }
 
 hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream) {
@@ -1260,7 +1332,7 @@ hipError_t launch_screen(int fmt, const ScreenArgs &a, hipStream_t stream) {
       return cf32 ? launch_windows<FMT_CF32, false>(w, a, stream) : launch_windows<FMT_CF16, false>(w, a, stream);
     }
     case kLong: return cf32 ? launch_long<FMT_CF32>(a, stream) : launch_long<FMT_CF16>(a, stream);
-    case kGeneric: return cf32 ? launch_generic<FMT_CF32>(a, stream) : launch_generic<FMT_CF16>(a, stream);
+    case kWide: return cf32 ? launch_wide<FMT_CF32>(a, stream) : launch_wide<FMT_CF16>(a, stream);
     default: return hipErrorInvalidValue;
   }
 }

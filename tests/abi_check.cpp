@@ -49,8 +49,13 @@ static void kernel_choice() {
   EXPECT(kernel_for(67, 1, c32, false) == kWindows && kernel_for(127, 1, c16, false) == kWindows);
   EXPECT(kernel_for(100, 1, c32, false) == kWindows && kernel_for(15, 2, c16, false) == kWindows);
   EXPECT(kernel_for(61, 1, c32, false) == kWindows && kernel_for(61, 1, c16, false) == kWindows);
-  EXPECT(kernel_for(8192, 2, c32, false) == kGeneric && kernel_for(300, 2, c16, false) == kGeneric);  // > 64 lanes
-  EXPECT(kernel_for(129, 4, c16, false) == kGeneric && kernel_for(200, 4, c32, false) == kGeneric);
+  EXPECT(kernel_for(8192, 2, c32, false) == kWide && kernel_for(300, 2, c16, false) == kWide);  // > 64 lanes
+  EXPECT(kernel_for(129, 4, c16, false) == kWide && kernel_for(200, 4, c32, false) == kWide);
+  EXPECT(kernel_for(256, 2, c16, false) == kWindows && kernel_for(257, 2, c16, false) == kWide);
+  // chunks of 64 C samples: 300 = 5 x 60 lanes (94 %), 8192 = 16 chunks of 512, 129 on 64 x 4
+  EXPECT(wide_chunk(300, c16) == 5 && wide_chunk(8192, c16) == 8 && wide_chunk(129, c16) == 4);
+  EXPECT(wide_chunk(200, c32) == 4 && wide_chunk(8192, c32) == 4 && wide_chunk(257, c32) == 3);
+  EXPECT(wide_chunk(1000, c16) == 8 && wide_chunk(600, c16) == 5);
   // lane layouts: (samples per lane, padded, share of lane slots)
   const WindowsLayout l100 = windows_layout(100, 1, c16, false), l100b = windows_layout(100, 1, c32, false);
   EXPECT(l100.C == 7 && l100.pad && l100.share > 0.89 && l100.share < 0.90);   // 15 runs on 16 lanes
@@ -59,7 +64,7 @@ static void kernel_choice() {
   EXPECT(windows_layout(48, 1, c32, false).C == 6 && !windows_layout(48, 1, c32, false).pad);
   EXPECT(windows_layout(50, 1, c16, false).C == 7 && windows_layout(61, 1, c16, false).C == 8);
   EXPECT(windows_layout(100, 1, c32, true).C == 0 && windows_layout(10, 2, c32, true).C == 5);
-  EXPECT(kernel_for(1000, 2, c16, false) == kGeneric);
+  EXPECT(kernel_for(1000, 2, c16, false) == kWide);
   EXPECT(kernel_for(10, 2, c32, true) == kWindows && kernel_for(64, 1, c32, true) == kWindows);
   EXPECT(kernel_for(10, 2, c16, true) == kNone && kernel_for(1024, 1, c32, true) == kNone);
   EXPECT(kernel_for(100, 1, c32, true) == kNone);  // mixed precision: whole power-of-two lane groups only

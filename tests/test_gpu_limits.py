@@ -26,8 +26,8 @@ def _gpu():
 def test_longest_windows(fmt, M, F, n_windows):
     """M = 4096 is the longest window of the tiled kernel (several steps per window, segments);
     M = 8192 of one channel goes to the long-window kernel, and over two channels (16384
-    samples per window) to the one-lane-per-window kernel, whose compensated sums keep the
-    error from growing with the window."""
+    samples per window) to the wide-window kernel (32 steps of 512 or 256 samples per window,
+    step sums added into the window sums, so no lane sums more than 40 terms in a row)."""
     T = M * n_windows
     vis = scene_vis(2, 2, T, seed=M + n_windows + F, duty=(300, 40))
     if fmt == "cf32":

@@ -207,16 +207,20 @@ def test_long_windows(fmt, M, T, N):
 
 
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
-@pytest.mark.parametrize("M,F,C,T", [(300, 2, 4, 1200), (129, 4, 4, 516)])
-def test_one_lane_per_window_lengths(fmt, M, F, C, T):
-    """Windows wider than 64 lanes of runs of at most 8 samples (300 x 2, 129 x 4): one lane per
-    window, its sums compensated."""
+@pytest.mark.parametrize("M,F,C,T", [(300, 2, 4, 1200), (129, 4, 4, 516), (1000, 2, 4, 3000), (600, 2, 2, 1800),
+                                     (257, 2, 4, 1028), (200, 4, 4, 800), (300, 2, 2, 300), (513, 4, 4, 1026)])
+def test_wide_windows(fmt, M, F, C, T):
+    """Time x frequency windows wider than 64 lanes of runs of 8 samples: a window over F R steps of
+    one chunk (64 C samples) of one channel each.  Runs that fill part of one chunk (300 x 2 on 60
+    of 64 lanes, 129 x 4 on 33), several chunks with a partial last one (1000 x 2: 512 + 488 in
+    complex half; 600 x 2, 257 x 2 in complex64), one window per stream (T = M), and 513 x 4
+    (chunks of 320 + 193 complex-half samples, 3 chunks of 192, the last 129, complex64)."""
     vis = scene_vis(2, C, T, seed=M * 3 + F, duty=(120, 25))
     if fmt == "cf32":
         op, gpu = screen_both(vis, M, F=F, **thresholds_for(M * F))
-        compare(gpu, vis, op, TOL_F32, label=f"one lane cf32 {M}x{F}")
+        compare(gpu, vis, op, TOL_F32, label=f"wide cf32 {M}x{F}")
     else:
-        check_cf16(vis, M, f"one lane cf16 {M}x{F}", F=F, **thresholds_for(M * F))
+        check_cf16(vis, M, f"wide cf16 {M}x{F}", F=F, **thresholds_for(M * F))
 
 
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
