@@ -51,10 +51,10 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(n_streams: int, T: int, M: int, sample_bytes: int) -> int:
-    """Bytes one screen must move: every sample read once, one flag byte per window,
-    average (8 floats) and weight (1 float) per stream."""
-    return n_streams * (T * sample_bytes + T // M + 36)
+def algorithmic_bytes(n_streams: int, T: int, M: int, sample_bytes: int, F: int = 1) -> int:
+    """Bytes one screen must move: every sample read once, one flag byte per window (of F
+    channels), average (8 floats) and weight (1 float) per stream."""
+    return n_streams * (T * sample_bytes + 36) + n_streams // F * (T // M)
 
 
 # ----------------------------------------------------------------------------- CPU baseline
@@ -303,7 +303,7 @@ def tf_window_form(steps: int, warmup: int, refs=None):
     """The paper's own window shape, 10 time samples x 2 channels (W = 20), on a 48-station,
     64-channel integration of 3000 samples (T divisible by 10), complex64 and complex half, and
     the paper's mixed precision (Tables 3-4); then M = 100 on the same array (complex64 and
-    complex half), a length with no exact lane layout.  With ``refs`` (precision_references) the
+    complex half), a length with no exact lane layout, and 300 x 2, a window wider than 64 lanes.  With ``refs`` (precision_references) the
     sampled baselines carry the oracle's input bytes, and each form's statistics and flags
     are compared with the FP64 oracle's after its timing."""
     import torch
@@ -349,24 +349,27 @@ def tf_window_form(steps: int, warmup: int, refs=None):
         res["vs_fp64_oracle"] = prec
     # a window length with no exact lane layout on the same array: M = 100 time samples (complex
     # half: 15 runs of 7 samples on 16 lanes, the last run zero-padded; complex64: 25 runs of 4
-    # on 32 lanes)
-    res["window_100"] = {}
-    for name, fmt, sb in (("cf32", rfi.RFI_VIS_CF32, 32), ("cf16", rfi.RFI_VIS_CF16, 16)):
-        vis = vis32 if fmt == rfi.RFI_VIS_CF32 else vis32.to(torch.float16)
-        params = rfi.rfi_params_default(n_stations=N_STATIONS, n_baselines=B, n_channels=C, n_samples=T,
-                                        block_m=100, vis_format=fmt, sk_d=2.2, sk_low=0.55, sk_high=1.55,
-                                        ds_gamma=0.16)
-        plan = rfi.Plan(params)
-        outs = plan.alloc_outputs(flags=True, stats=False)
-        with torch.cuda.stream(stream):
-            per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup, f"window_100.{name}")
-        plan.close()
-        alg = algorithmic_bytes(B * C, T, 100, sb)
-        res["window_100"][name] = {"samples_per_s": B * C * T * steps / (total_ms * 1e-3),
-                                   "kernel_ms_mean": float(per.mean()),
-                                   "achieved_GBs": alg / (per.mean() * 1e-3) / 1e9,
-                                   "hbm_frac": alg / (per.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        del vis
+    # on 32 lanes); and a time x frequency window wider than 64 lanes of runs of 8, 300 x 2 (a
+    # window over 2 steps of one channel's 300 samples each: complex half 5 per lane on 60 lanes,
+    # complex64 2 chunks of 192)
+    for key, M, F, th in (("window_100", 100, 1, dict(sk_d=2.2, sk_low=0.55, sk_high=1.55, ds_gamma=0.16)),
+                          ("window_300x2", 300, 2, dict(sk_d=2.2, sk_low=0.8, sk_high=1.25, ds_gamma=0.07))):
+        res[key] = {}
+        for name, fmt, sb in (("cf32", rfi.RFI_VIS_CF32, 32), ("cf16", rfi.RFI_VIS_CF16, 16)):
+            vis = vis32 if fmt == rfi.RFI_VIS_CF32 else vis32.to(torch.float16)
+            params = rfi.rfi_params_default(n_stations=N_STATIONS, n_baselines=B, n_channels=C, n_samples=T,
+                                            block_m=M, block_f=F, vis_format=fmt, **th)
+            plan = rfi.Plan(params)
+            outs = plan.alloc_outputs(flags=True, stats=False)
+            with torch.cuda.stream(stream):
+                per, total_ms, _ = time_form(plan, vis, outs, stream, steps, warmup, f"{key}.{name}")
+            plan.close()
+            alg = algorithmic_bytes(B * C, T, M, sb, F)
+            res[key][name] = {"samples_per_s": B * C * T * steps / (total_ms * 1e-3),
+                              "kernel_ms_mean": float(per.mean()),
+                              "achieved_GBs": alg / (per.mean() * 1e-3) / 1e9,
+                              "hbm_frac": alg / (per.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            del vis
     del vis32
     torch.cuda.empty_cache()
     return res

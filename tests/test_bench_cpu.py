@@ -24,6 +24,8 @@ def test_more_than_one_gpu_is_refused(capsys):
 def test_algorithmic_bytes():
     # the FP32 baseline: 75 264 streams x (3072 x 32 B + 48 flag bytes + 36 B of average and weight)
     assert bench.algorithmic_bytes(1176 * 64, 3072, 64, 32) == 1176 * 64 * (3072 * 32 + 48 + 36) == 7405074432
+    # windows of 10 x 2: one flag byte per window of a channel pair
+    assert bench.algorithmic_bytes(1176 * 64, 3000, 10, 16, F=2) == 1176 * 64 * (3000 * 16 + 36) + 1176 * 32 * 300
 
 
 def test_stat_errors_count_one_sided_non_finite_apart():
