@@ -796,124 +796,204 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a, int
   }
   const int my_piece = act ? f * ch_tile + (j * S * C + s * C) * PPS : 0;
 
-  // PERSIST: block b screens the channel groups [b U, (b + 1) U) (its waves take every fourth)
-  // and keeps their flags in LDS until the last is done, then writes them in one pass
-  const int64_t first = PERSIST ? (int64_t)blockIdx.x * U : 0;
-  const int64_t last = PERSIST ? min(first + (int64_t)U, a.n_groups) : 0;
-  for (int64_t group = PERSIST ? first + wave : (int64_t)blockIdx.x * kWavesPerBlock + wave;;
-       group += kWavesPerBlock) {
-    const bool active = group < (PERSIST ? last : a.n_groups);
-    if (PERSIST && !active) break;
-    StreamAcc<1> acc{};                         // this lane's channel: masked sums, kept, moments
-    if (active) {
-      const Thresholds th = stream_thresholds(a, group);
-      const uint8_t *base = a.vis + group * F * (int64_t)a.T * SB;
-      const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<uint8_t *>(base), (short)0, F * a.T * SB, kRsrcWord3);
-      u32x4 buf[P] = {};                        // a piece the last step leaves unread keeps its old value
-      auto issue = [&](int step) {
-        const int soff = step * ch_samples * SB;
-        const int room = step == n_steps - 1 ? a.T - step * ch_samples : ch_samples;  // uniform
+  // Steps [st0, st1) of channel group `group` into acc: flags and statistics of their windows
+  // written (to LDS at lds_flags + (w - lds_w0) when lds_flags is set), raw sums of the clean
+  // windows folded into this lane's channel sum.
+  auto screen_steps = [&](int64_t group, int st0, int st1, StreamAcc<1> &acc, uint8_t *lds_flags,
+                          int64_t lds_w0) {
+    const Thresholds th = stream_thresholds(a, group);
+    const uint8_t *base = a.vis + group * F * (int64_t)a.T * SB;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t *>(base), (short)0, F * a.T * SB, kRsrcWord3);
+    u32x4 buf[P] = {};                          // a piece the last step leaves unread keeps its old value
+    auto issue = [&](int step) {
+      const int soff = step * ch_samples * SB;
+      const int room = step == n_steps - 1 ? a.T - step * ch_samples : ch_samples;  // uniform
 #pragma unroll
-        for (int i = 0; i < P; ++i)
-          if ((!PAD || slot[i] >= 0) && (F == 1 || tpos[i] < room))
-            buf[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i], soff, kLoadStreaming));
-      };
-      issue(0);
-      for (int step = 0; step < n_steps; ++step) {
-        wave_lds_order();
+      for (int i = 0; i < P; ++i)
+        if ((!PAD || slot[i] >= 0) && (F == 1 || tpos[i] < room))
+          buf[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i], soff, kLoadStreaming));
+    };
+    issue(st0);
+    for (int step = st0; step < st1; ++step) {
+      wave_lds_order();
 #pragma unroll
-        for (int i = 0; i < P; ++i) {
-          if constexpr (PAD) {
-            if (slot[i] >= 0) my_tile[slot[i]] = buf[i];
-          } else {
-            my_tile[i * kWave + lane] = buf[i];
-          }
-        }
-        wave_lds_order();
-        if (step + 1 < n_steps) issue(step + 1);
-        float ws[8] = {}, wr[8] = {};
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-          if (!act) break;                      // PAD: a lane left over in its group
-          if constexpr (FMT == FMT_CF32) {
-            const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k]);
-            const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k + 1]);
-            const float x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-            if constexpr (MIXED)
-              accumulate_sample_mixed(ws, wr, x, a.eps);
-            else if (!PAD && k == 0)            // every lane holds C samples: the first starts the sums
-              accumulate_sample<true>(ws, wr, x, a.eps);
-            else
-              accumulate_sample(ws, wr, x, a.eps);
-          } else {
-            static_assert(!MIXED, "the paper's mixed precision takes complex64 input");
-            if (!PAD && k == 0)
-              accumulate_sample_h<true>(ws, wr, my_tile[my_piece + k], a.eps);
-            else
-              accumulate_sample_h(ws, wr, my_tile[my_piece + k], a.eps);
-          }
-        }
-        group_sum8_rt<MIXED ? 2 : 8>(ws, L);   // ws now holds the window totals
-        const int w = step * wps + j;
-        const bool valid = w < a.nW;
-        // one lane per window plays the leader of finish_window (kept count, moments, flag and
-        // statistics); every lane folds its own raw partial into its own channel's sum
-        const float wr1[1][8] = {{wr[0], wr[1], wr[2], wr[3], wr[4], wr[5], wr[6], wr[7]}};
-        if constexpr (MIXED) {
-          Thresholds t16{round16(th.s_low), round16(th.s_high), round16(th.g_re), round16(th.g_im)};
-          finish_window<1, true>(a, t16, ws, wr1, group * a.nW + w, valid, g == 0, acc,
-                                 PERSIST ? block_flags : nullptr, first * a.nW);
+      for (int i = 0; i < P; ++i) {
+        if constexpr (PAD) {
+          if (slot[i] >= 0) my_tile[slot[i]] = buf[i];
         } else {
-          finish_window<1>(a, th, ws, wr1, group * a.nW + w, valid, g == 0, acc,
-                           PERSIST ? block_flags : nullptr, first * a.nW);
+          my_tile[i * kWave + lane] = buf[i];
         }
       }
+      wave_lds_order();
+      if (step + 1 < st1) issue(step + 1);
+      float ws[8] = {}, wr[8] = {};
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        if (!act) break;                        // PAD: a lane left over in its group
+        if constexpr (FMT == FMT_CF32) {
+          const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k]);
+          const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k + 1]);
+          const float x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+          if constexpr (MIXED)
+            accumulate_sample_mixed(ws, wr, x, a.eps);
+          else if (!PAD && k == 0)              // every lane holds C samples: the first starts the sums
+            accumulate_sample<true>(ws, wr, x, a.eps);
+          else
+            accumulate_sample(ws, wr, x, a.eps);
+        } else {
+          static_assert(!MIXED, "the paper's mixed precision takes complex64 input");
+          if (!PAD && k == 0)
+            accumulate_sample_h<true>(ws, wr, my_tile[my_piece + k], a.eps);
+          else
+            accumulate_sample_h(ws, wr, my_tile[my_piece + k], a.eps);
+        }
+      }
+      group_sum8_rt<MIXED ? 2 : 8>(ws, L);     // ws now holds the window totals
+      const int w = step * wps + j;
+      const bool valid = w < a.nW;
+      // one lane per window plays the leader of finish_window (kept count, moments, flag and
+      // statistics); every lane folds its own raw partial into its own channel's sum
+      const float wr1[1][8] = {{wr[0], wr[1], wr[2], wr[3], wr[4], wr[5], wr[6], wr[7]}};
+      if constexpr (MIXED) {
+        Thresholds t16{round16(th.s_low), round16(th.s_high), round16(th.g_re), round16(th.g_im)};
+        finish_window<1, true>(a, t16, ws, wr1, group * a.nW + w, valid, g == 0, acc, lds_flags, lds_w0);
+      } else {
+        finish_window<1>(a, th, ws, wr1, group * a.nW + w, valid, g == 0, acc, lds_flags, lds_w0);
+      }
     }
-    // masked sums: reduce over the lanes of each channel
-    float chan[PAD ? F : 1][8];
+  };
+
+  // The wave's results for one group, reduced over its lanes into lane 0: channel sums (F x 8),
+  // kept count, moments.
+  auto reduce_group = [&](const StreamAcc<1> &acc, float sums[F][8], float &kept, Moments &mom) {
     if constexpr (PAD) {                        // channel bits are not lane bits: masked wave sums
 #pragma unroll
       for (int c = 0; c < F; ++c)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) chan[c][e] = group_sum<64>(act && f == c ? acc.sum[0][e] : 0.0f);
-    } else {                                    // skip the f bits of the lane index
-#pragma unroll
+        for (int e = 0; e < 8; ++e) sums[c][e] = group_sum<64>(act && f == c ? acc.sum[0][e] : 0.0f);
+    } else {                                    // skip the f bits of the lane index, then lane c S
+#pragma unroll                                  // holds channel c
       for (int e = 0; e < 8; ++e) {
         float v = acc.sum[0][e];
         for (int m = 1; m < kWave; m <<= 1)
           if (m < S || m >= L) v += __shfl_xor(v, m);
-        chan[0][e] = v;
+#pragma unroll
+        for (int c = 0; c < F; ++c) sums[c][e] = __shfl(v, c * S);
       }
     }
-    const float kept = group_sum<64>(acc.kept);
-    Moments mom = acc.mom;
+    kept = group_sum<64>(acc.kept);
+    mom = acc.mom;
     if (a.state != nullptr) {
 #pragma unroll
       for (int m = 1; m < kWave; m <<= 1) mom = moments_merge(mom, moments_shfl_xor(mom, m));
     }
-    if (active) {
-      const float inv = kept > 0.0f ? 1.0f / kept : 0.0f;
-      auto write_channel = [&](int c, const float v[8]) {
-        const int64_t stream = group * F + c;
-        f32x4 *out = reinterpret_cast<f32x4 *>(a.avg + stream * 8);
-        out[0] = f32x4{v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv};
-        out[1] = f32x4{v[4] * inv, v[5] * inv, v[6] * inv, v[7] * inv};
-        a.weight[stream] = kept * a.invT;
-      };
-      if constexpr (PAD) {
-        if (lane == 0)
+  };
+
+  // Average, weight and adaptive state of a whole group (lane 0's values).
+  auto write_group = [&](int64_t group, const float sums[F][8], float kept, const Moments &mom) {
+    const float inv = kept > 0.0f ? 1.0f / kept : 0.0f;
 #pragma unroll
-          for (int c = 0; c < F; ++c) write_channel(c, chan[c]);
-      } else if (lane < L && s == 0) {          // lane f S of window 0 writes channel f
-        write_channel(f, chan[0]);
-      }
-      if (lane == 0 && a.state != nullptr && mom.n > 0u) state_merge(a.state + group, mom);
+    for (int c = 0; c < F; ++c) {
+      const int64_t stream = group * F + c;
+      f32x4 *out = reinterpret_cast<f32x4 *>(a.avg + stream * 8);
+      out[0] = f32x4{sums[c][0] * inv, sums[c][1] * inv, sums[c][2] * inv, sums[c][3] * inv};
+      out[1] = f32x4{sums[c][4] * inv, sums[c][5] * inv, sums[c][6] * inv, sums[c][7] * inv};
+      a.weight[stream] = kept * a.invT;
     }
-    if (!PERSIST) break;
-  }
-  if constexpr (PERSIST) {
+    if (a.state != nullptr && mom.n > 0u) state_merge(a.state + group, mom);
+  };
+
+  if constexpr (!PERSIST) {                     // one wave per channel group
+    const int64_t group = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    StreamAcc<1> acc{};
+    if (group < a.n_groups) screen_steps(group, 0, n_steps, acc, nullptr, 0);
+    float sums[F][8], kept;
+    Moments mom;
+    reduce_group(acc, sums, kept, mom);
+    if (group < a.n_groups && lane == 0) write_group(group, sums, kept, mom);
+  } else {
+    // Block b screens the channel groups [first, last) = [b U, (b + 1) U), or with U = 0
+    // [b n / G, (b + 1) n / G) (n groups, G blocks: the blocks differ by at most one group).  Its
+    // waves take the groups in rounds of four, whole (wave w every fourth from first + w), and
+    // split the steps of the last (last - first) mod 4 groups evenly, each a contiguous run of
+    // them; a group split between waves leaves each a partial record (channel sums, kept count,
+    // moments) in LDS, merged once the block is done.  The block's flags stay in LDS until then
+    // and are written in one pass, after the reads.
+    __shared__ float rec[2 * kWavesPerBlock][kXfer];
+    __shared__ int64_t rec_group[2 * kWavesPerBlock];
+    const int64_t nb = gridDim.x;
+    const int64_t first = U > 0 ? (int64_t)blockIdx.x * U : (int64_t)blockIdx.x * a.n_groups / nb;
+    const int64_t last = U > 0 ? min(first + U, a.n_groups) : ((int64_t)blockIdx.x + 1) * a.n_groups / nb;
+    if (threadIdx.x < 2 * kWavesPerBlock) rec_group[threadIdx.x] = -1;
     __syncthreads();
+    const int64_t split0 = first + (last - first) / kWavesPerBlock * kWavesPerBlock;
+    for (int64_t group = first + wave; group < split0; group += kWavesPerBlock) {
+      StreamAcc<1> acc{};
+      screen_steps(group, 0, n_steps, acc, block_flags, first * a.nW);
+      float sums[F][8], kept;
+      Moments mom;
+      reduce_group(acc, sums, kept, mom);
+      if (lane == 0) write_group(group, sums, kept, mom);
+    }
+    const int64_t total = (last - split0) * n_steps;
+    const int64_t s_end = total * (wave + 1) / kWavesPerBlock;
+    int n_rec = 0;
+    for (int64_t s0 = total * wave / kWavesPerBlock; s0 < s_end;) {
+      const int64_t gi = s0 / n_steps;
+      const int st0 = (int)(s0 - gi * n_steps);
+      const int st1 = (int)min((int64_t)n_steps, st0 + (s_end - s0));
+      const int64_t group = split0 + gi;
+      StreamAcc<1> acc{};
+      screen_steps(group, st0, st1, acc, block_flags, first * a.nW);
+      float sums[F][8], kept;
+      Moments mom;
+      reduce_group(acc, sums, kept, mom);
+      if (st0 == 0 && st1 == n_steps) {         // the whole group in this wave
+        if (lane == 0) write_group(group, sums, kept, mom);
+      } else if (lane == 0) {                   // at most two per wave: its first and its last group
+        const int r = 2 * wave + n_rec;
+#pragma unroll
+        for (int c = 0; c < F; ++c)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) rec[r][8 * c + e] = sums[c][e];
+        rec[r][32] = kept;
+        rec[r][33] = __uint_as_float(mom.n);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          rec[r][34 + k] = mom.m[k];
+          rec[r][37 + k] = mom.s[k];
+        }
+        rec_group[r] = group;
+      }
+      if (!(st0 == 0 && st1 == n_steps)) ++n_rec;
+      s0 += st1 - st0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {                     // groups split between waves: merge the records
+      for (int r = 0; r < 2 * kWavesPerBlock; ++r) {
+        const int64_t group = rec_group[r];
+        if (group < 0) continue;
+        float sums[F][8], kept = rec[r][32];
+        Moments mom{__float_as_uint(rec[r][33]), {rec[r][34], rec[r][35], rec[r][36]}, {rec[r][37], rec[r][38], rec[r][39]}};
+#pragma unroll
+        for (int c = 0; c < F; ++c)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) sums[c][e] = rec[r][8 * c + e];
+        for (int q = r + 1; q < 2 * kWavesPerBlock; ++q) {
+          if (rec_group[q] != group) continue;
+#pragma unroll
+          for (int c = 0; c < F; ++c)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sums[c][e] += rec[q][8 * c + e];
+          kept += rec[q][32];
+          const Moments b{__float_as_uint(rec[q][33]), {rec[q][34], rec[q][35], rec[q][36]}, {rec[q][37], rec[q][38], rec[q][39]}};
+          mom = moments_merge(mom, b);
+          rec_group[q] = -1;
+        }
+        write_group(group, sums, kept, mom);
+      }
+    }
     if (a.flags != nullptr) {
       const int64_t base = first * a.nW, n = (last - first) * a.nW;
       for (int64_t i = threadIdx.x; i < n; i += kBlock) a.flags[base + i] = block_flags[i];
@@ -1177,20 +1257,29 @@ hipError_t launch_windows_k(const ScreenArgs &a, hipStream_t stream) {
   constexpr int tile_bytes = kWavesPerBlock * kWave * C * (FMT == FMT_CF32 ? 2 : 1) * 16;
   constexpr unsigned pad = FMT == FMT_CF16 && !PAD && !MIXED && C >= 5 && tile_bytes < kFourBlocksLds
                                ? (unsigned)(kFourBlocksLds - tile_bytes) : 0u;
-  // complex64 exact layouts of at most 6 samples per lane (the paper's mixed form included) with
-  // a flag array run persistent: each block screens a range of channel groups and writes their
-  // flags, held in LDS, once they are done, at the most blocks per CU (4, 3, 2) whose flag range
-  // fits beside the tile (two for runs of 5: 10 x 2 +5.5 %, 5 x 4 +5.1 %, M = 20 +4.5 %, the mixed
-  // form +3.4 %; M = 48 +1.1 %; runs of 8, 16 x 2, -3.1 %).  Complex half gains nothing that way
-  // (10 x 2 +0 %, 5 x 4 +1.4 %, M = 20 -1.4 %) and padded layouts lose 2-6 %: one wave per group.
-  if constexpr (FMT == FMT_CF32 && !PAD && C <= 6) {
-    for (int bpc = 4; bpc >= 2 && a.flags != nullptr && a.n_cu > 0; --bpc) {
-      const int64_t G = (int64_t)a.n_cu * bpc;
-      const int64_t U = balanced_share(a.n_groups, G);
-      const int64_t room = 163840 / bpc - 512 - tile_bytes;
-      if (U * a.nW <= room) {
-        const int64_t blocks = (a.n_groups + U - 1) / U;
-        const unsigned lds = (unsigned)std::max<int64_t>(U * a.nW, (int64_t)pad);
+  // Exact layouts of at most 6 samples per lane with a flag array run persistent, each block's
+  // flags held in LDS until its groups are done, at the most blocks per CU (4, 3, 2) whose flags
+  // fit beside the tile.  Complex64 (the paper's mixed form included): U groups per block, a
+  // multiple of the four waves, so each wave screens whole groups (10 x 2 +5.5 %, 5 x 4 +5.1 %,
+  // M = 20 +4.5 %, the mixed form +3.4 %, M = 48 +1.1 % over one wave per group; runs of 8 lose
+  // 3 %).  Complex half, whose VALU-heavy waves run as fast as their CU lets them, needs the same
+  // work on every CU: G = blocks per CU x CUs blocks of n / G groups, the steps of each block's
+  // last (n / G) mod 4 groups split between its waves; and only where a group has at least 16
+  // steps (5 x 4 +2.2 to +3.8 %, 10 x 2 +0.2 to +1.6 %; M = 20 and 48, 8-10 steps per group, lost
+  // 1-4 %).  Interleaved whole groups matter to complex64: contiguous runs of groups per wave cost
+  // it 0.6-2 %.
+  if constexpr (!PAD && C <= 6) {
+    constexpr int rec_bytes = 2 * kWavesPerBlock * (kXfer * 4 + 8);
+    const int L = a.F * (a.M / C), wps = kWave / L;
+    const bool long_groups = (a.nW + wps - 1) / wps >= 16;
+    for (int bpc = 4; bpc >= 2 && a.flags != nullptr && a.n_cu > 0 && (FMT == FMT_CF32 || long_groups); --bpc) {
+      const int64_t G = std::min<int64_t>((int64_t)a.n_cu * bpc, a.n_groups);
+      const int64_t U = FMT == FMT_CF32 ? balanced_share(a.n_groups, G) : 0;
+      const int64_t blocks = U > 0 ? (a.n_groups + U - 1) / U : G;
+      const int64_t most = U > 0 ? U : (a.n_groups + G - 1) / G;   // groups of the largest block
+      const int64_t room = 163840 / bpc - 512 - tile_bytes - rec_bytes;
+      if (most * a.nW <= room) {
+        const unsigned lds = (unsigned)std::max<int64_t>(most * a.nW, (int64_t)pad);
         return launch_windows_f<FMT, C, MIXED, PAD, true>(dim3((unsigned)blocks), lds, (int)U, a, stream);
       }
     }
