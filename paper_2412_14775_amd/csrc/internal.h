@@ -64,7 +64,7 @@ constexpr int kMaxTiledLog2M = 12;  // tiled kernels exist for M = 2 .. 4096
 // not apply, or when the layout fills at least kPadOverLong of its lane slots; long (F = 1,
 // M more than half a step: 128 complex64 / 256 complex-half samples); otherwise (F > 1,
 // windows wider than 64 lanes) the wide-window kernel, a window over several steps of one
-// channel chunk each.  The paper's mixed precision exists only in the windowed kernel on exact
+// channel chunk each (F = 4 with runs within 32 lanes: two channels' runs per step).  The paper's mixed precision exists only in the windowed kernel on exact
 // layouts with complex64 storage (kNone elsewhere).  The tiled and long kernels may split a
 // stream into window-aligned segments (one wave each).
 enum KernelKind { kTiled, kWindows, kLong, kWide, kNone };
@@ -72,6 +72,8 @@ KernelKind kernel_for(int M, int F, int fmt, bool mixed);
 
 // Samples per lane of the wide-window kernel's chunks (64 C samples of one channel's run).
 int wide_chunk(int M, int fmt);
+// Samples per lane of its two-runs-per-step form (F = 4, runs within 32 lanes), or 0.
+int wide_pairs_chunk(int M, int fmt);
 
 // Lane layout of the windowed kernel: C samples per lane, padded (pad) or exact, and the
 // share of its lane slots that hold samples.  C = 0: the windowed kernel does not apply.

@@ -1110,6 +1110,128 @@ __global__ void __launch_bounds__(kBlock) screen_wide(const ScreenArgs a) {
   finish_stream<F>(a, acc, group, 0, active, wave, lane, xfer);
 }
 
+// Wide windows over four channels whose runs fit 32 lanes (M <= 32 C): a step holds the runs of
+// two channels of a window, lanes [0, S) channel 2p and [S, 2S) channel 2p + 1 (S = ceil(M / C),
+// p = 0, 1), so a window is two steps, fewer lanes stand idle than with one run per step (129 x 4:
+// 52 of 64 lanes on runs of 5 where one run of 4 per step used 33), and a lane keeps the raw sums
+// of two channels.  Each run takes S C tile slots; the slots past M stay zero (written once, never
+// loaded), as do the lanes past 2 S.
+template <int FMT, int C>
+__global__ void __launch_bounds__(kBlock) screen_wide_pairs(const ScreenArgs a) {
+  constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
+  constexpr int PPS = SB / 16;                  // 16-byte pieces per sample
+  constexpr int P = C * PPS;                    // pieces per lane per step
+  constexpr int F = 4;
+  __shared__ u32x4 tile[kWavesPerBlock][kWave * P];
+
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int64_t group = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const bool active = group < a.n_groups;
+  const int S = (a.M + C - 1) / C;              // lanes per run, <= 32
+  const int h = lane / S;                       // the lane's channel of the pair (2, 3, ...: idle)
+  const bool act = h < 2;
+  const int my_piece = act ? lane * C * PPS : 0;  // (h S + s) C PPS
+  u32x4 *my_tile = tile[wave];
+  // piece q = i 64 + lane of a step, q < 2 M PPS: run hq = q / (M PPS), piece r of it; its byte
+  // offset in the group (the step adds the pair's channel and the window as a scalar) and its
+  // tile slot, fixed for the kernel
+  int voff[P], lslot[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int q = i * kWave + lane;
+    my_tile[i * kWave + lane] = u32x4{0u, 0u, 0u, 0u};
+    voff[i] = 0;
+    lslot[i] = -1;
+    if (q < 2 * a.M * PPS) {
+      const int hq = q / (a.M * PPS), r = q - hq * a.M * PPS;
+      voff[i] = hq * a.T * SB + r * 16;         // < 2 T SB
+      lslot[i] = hq * S * C * PPS + r;
+    }
+  }
+  StreamAcc<2> acc{};                           // acc.sum[p]: channel 2 p + h
+  if (active) {
+    const Thresholds th = stream_thresholds(a, group);
+    const uint8_t *base = a.vis + group * F * (int64_t)a.T * SB;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t *>(base), (short)0, F * a.T * SB, kRsrcWord3);
+    u32x4 buf[P] = {};
+    auto issue = [&](int j, int p) {            // channels 2 p, 2 p + 1 of window j
+      const int soff = (2 * p * a.T + j * a.M) * SB;
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        if (lslot[i] >= 0)
+          buf[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[i], soff, kLoadStreaming));
+    };
+    float ws[8] = {}, wr[2][8] = {};
+    issue(0, 0);
+    for (int j = 0; j < a.nW; ++j) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        wave_lds_order();
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+          if (lslot[i] >= 0) my_tile[lslot[i]] = buf[i];
+        wave_lds_order();
+        if (p == 0)
+          issue(j, 1);
+        else if (j + 1 < a.nW)
+          issue(j + 1, 0);
+        float ps[8] = {}, pr[8] = {};
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+          if (!act) break;
+          if constexpr (FMT == FMT_CF32) {
+            const f32x4 lo = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k]);
+            const f32x4 hi = __builtin_bit_cast(f32x4, my_tile[my_piece + 2 * k + 1]);
+            const float x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            accumulate_sample(ps, pr, x, a.eps);
+          } else {
+            accumulate_sample_h(ps, pr, my_tile[my_piece + k], a.eps);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          ws[k] += ps[k];
+          wr[p][k] += pr[k];
+        }
+      }
+      float tot[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) tot[k] = group_sum<kWave>(ws[k]);
+      finish_window<2>(a, th, tot, wr, group * a.nW + j, true, lane == 0, acc);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) ws[k] = wr[0][k] = wr[1][k] = 0.0f;
+    }
+  }
+  // channel 2 p + hh: masked wave sums of acc.sum[p] over the lanes of run hh
+  float chan[F][8];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) chan[2 * p + hh][e] = group_sum<kWave>(act && h == hh ? acc.sum[p][e] : 0.0f);
+  const float kept = group_sum<kWave>(acc.kept);
+  Moments mom = acc.mom;
+  if (a.state != nullptr) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) mom = moments_merge(mom, moments_shfl_xor(mom, m));
+  }
+  if (active && lane == 0) {
+    const float inv = kept > 0.0f ? 1.0f / kept : 0.0f;
+#pragma unroll
+    for (int c = 0; c < F; ++c) {
+      const int64_t stream = group * F + c;
+      f32x4 *out = reinterpret_cast<f32x4 *>(a.avg + stream * 8);
+      out[0] = f32x4{chan[c][0] * inv, chan[c][1] * inv, chan[c][2] * inv, chan[c][3] * inv};
+      out[1] = f32x4{chan[c][4] * inv, chan[c][5] * inv, chan[c][6] * inv, chan[c][7] * inv};
+      a.weight[stream] = kept * a.invT;
+    }
+    if (a.state != nullptr && mom.n > 0u) state_merge(a.state + group, mom);
+  }
+}
+
 // Unused dynamic LDS that caps the complex64 tiled kernel at three blocks (12 waves) per CU
 // (33 KiB static + 7.5 KiB > 160 KiB / 4).  Its registers alone would allow 16 waves; with fewer
 // streams read at once the kernel streams 1-2 % faster.  The complex-half kernel is held at
@@ -1215,8 +1337,27 @@ hipError_t launch_wide_c(const ScreenArgs &a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+template <int FMT, int C>
+hipError_t launch_wide_pairs_c(const ScreenArgs &a, hipStream_t stream) {
+  const int64_t blocks = (a.n_groups + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL((screen_wide_pairs<FMT, C>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, a);
+  return hipGetLastError();
+}
+
 template <int FMT>
 hipError_t launch_wide(const ScreenArgs &a, hipStream_t stream) {
+  if (a.F == 4) {                               // runs that fit 32 lanes: two channels per step
+    switch (wide_pairs_chunk(a.M, FMT)) {
+      case 0: break;
+      case 3: if constexpr (FMT == FMT_CF32) return launch_wide_pairs_c<FMT, 3>(a, stream); break;
+      case 4: if constexpr (FMT == FMT_CF32) return launch_wide_pairs_c<FMT, 4>(a, stream); break;
+      case 5: if constexpr (FMT == FMT_CF16) return launch_wide_pairs_c<FMT, 5>(a, stream); break;
+      case 6: if constexpr (FMT == FMT_CF16) return launch_wide_pairs_c<FMT, 6>(a, stream); break;
+      case 7: if constexpr (FMT == FMT_CF16) return launch_wide_pairs_c<FMT, 7>(a, stream); break;
+      case 8: if constexpr (FMT == FMT_CF16) return launch_wide_pairs_c<FMT, 8>(a, stream); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
   if constexpr (FMT == FMT_CF32) {
     switch (wide_chunk(a.M, FMT)) {
       case 2: return launch_wide_c<FMT, 2>(a, stream);
@@ -1380,6 +1521,15 @@ int wide_chunk(int M, int fmt) {
     }
   }
   return best;
+}
+
+// Samples per lane of the two-runs-per-step wide kernel (F = 4): ceil(M / 32), the fewest that
+// fit a channel's run in 32 lanes, for complex half 5-8 (M = 129-256) and complex64 3-4
+// (M = 65-128); 0 where it does not apply.
+int wide_pairs_chunk(int M, int fmt) {
+  const int C = (M + 31) / 32;
+  const int lo = fmt == FMT_CF32 ? 3 : 5, hi = fmt == FMT_CF32 ? 4 : 8;
+  return C >= lo && C <= hi ? C : 0;
 }
 
 WindowsLayout windows_layout(int M, int F, int fmt, bool mixed) {

@@ -56,6 +56,11 @@ static void kernel_choice() {
   EXPECT(wide_chunk(300, c16) == 5 && wide_chunk(8192, c16) == 8 && wide_chunk(129, c16) == 4);
   EXPECT(wide_chunk(200, c32) == 4 && wide_chunk(8192, c32) == 4 && wide_chunk(257, c32) == 3);
   EXPECT(wide_chunk(1000, c16) == 8 && wide_chunk(600, c16) == 5);
+  // two runs per step (F = 4): the fewest samples per lane that fit a run in 32 lanes
+  EXPECT(wide_pairs_chunk(129, c16) == 5 && wide_pairs_chunk(200, c16) == 7 && wide_pairs_chunk(256, c16) == 8);
+  EXPECT(wide_pairs_chunk(257, c16) == 0 && wide_pairs_chunk(100, c16) == 0);
+  EXPECT(wide_pairs_chunk(81, c32) == 3 && wide_pairs_chunk(100, c32) == 4 && wide_pairs_chunk(129, c32) == 0);
+  EXPECT(kernel_for(100, 4, c32, false) == kWide && kernel_for(81, 4, c32, false) == kWide);
   // lane layouts: (samples per lane, padded, share of lane slots)
   const WindowsLayout l100 = windows_layout(100, 1, c16, false), l100b = windows_layout(100, 1, c32, false);
   EXPECT(l100.C == 7 && l100.pad && l100.share > 0.89 && l100.share < 0.90);   // 15 runs on 16 lanes

@@ -20,7 +20,8 @@ def _integration(i, N=2, C=8, T=1024):
                                              ("cf32", 20, 1, 1280, 80), ("cf16", 10, 2, 1280, 80),
                                              ("cf32", 300, 1, 1200, 8), ("cf16", 600, 1, 1200, 4),
                                              ("cf16", 100, 1, 1200, 20), ("cf32", 600, 1, 1200, 4),
-                                             ("cf16", 300, 2, 1200, 4), ("cf32", 200, 4, 1200, 3)])
+                                             ("cf16", 300, 2, 1200, 4), ("cf32", 200, 4, 1200, 3),
+                                             ("cf16", 200, 4, 1200, 3), ("cf32", 100, 4, 1200, 6)])
 def test_adaptive_thresholds_follow_oracle_state(fmt, M, F, T, n_warm):
     from paper_2412_14775_amd import rfi
     B, C = 3, 8

@@ -218,13 +218,17 @@ def test_long_windows(fmt, M, T, N):
 
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
 @pytest.mark.parametrize("M,F,C,T", [(300, 2, 4, 1200), (129, 4, 4, 516), (1000, 2, 4, 3000), (600, 2, 2, 1800),
-                                     (257, 2, 4, 1028), (200, 4, 4, 800), (300, 2, 2, 300), (513, 4, 4, 1026)])
+                                     (257, 2, 4, 1028), (200, 4, 4, 800), (300, 2, 2, 300), (513, 4, 4, 1026),
+                                     (100, 4, 4, 1000), (81, 4, 4, 810), (256, 4, 4, 512), (129, 4, 8, 129)])
 def test_wide_windows(fmt, M, F, C, T):
     """Time x frequency windows wider than 64 lanes of runs of 8 samples: a window over F R steps of
     one chunk (64 C samples) of one channel each.  Runs that fill part of one chunk (300 x 2 on 60
-    of 64 lanes, 129 x 4 on 33), several chunks with a partial last one (1000 x 2: 512 + 488 in
-    complex half; 600 x 2, 257 x 2 in complex64), one window per stream (T = M), and 513 x 4
-    (chunks of 320 + 193 complex-half samples, 3 chunks of 192, the last 129, complex64)."""
+    of 64 lanes, complex64 129 x 4 on 33), several chunks with a partial last one (1000 x 2: 512 +
+    488 in complex half; 600 x 2, 257 x 2 in complex64), one window per stream (T = M), and 513 x 4
+    (chunks of 320 + 193 complex-half samples, 3 chunks of 192, the last 129, complex64).  Four
+    channels whose runs fit 32 lanes take two runs per step: complex half 129 x 4 (runs of 5 on
+    26 + 26 lanes), 200 x 4 (7 on 29 + 29), 256 x 4 (8 on 32 + 32), complex64 100 x 4 (4 on 25 + 25)
+    and 81 x 4 (3 on 27 + 27; complex half 81 x 4 is a windowed layout)."""
     vis = scene_vis(2, C, T, seed=M * 3 + F, duty=(120, 25))
     if fmt == "cf32":
         op, gpu = screen_both(vis, M, F=F, **thresholds_for(M * F))
