@@ -1405,15 +1405,16 @@ hipError_t launch_windows_k(const ScreenArgs &a, hipStream_t stream) {
   // M = 20 +4.5 %, the mixed form +3.4 %, M = 48 +1.1 % over one wave per group; runs of 8 lose
   // 3 %).  Complex half, whose VALU-heavy waves run as fast as their CU lets them, needs the same
   // work on every CU: G = blocks per CU x CUs blocks of n / G groups, the steps of each block's
-  // last (n / G) mod 4 groups split between its waves; and only where a group has at least 16
-  // steps (5 x 4 +2.2 to +3.8 %, 10 x 2 +0.2 to +1.6 %; M = 20 and 48, 8-10 steps per group, lost
-  // 1-4 %).  Interleaved whole groups matter to complex64: contiguous runs of groups per wave cost
+  // last (n / G) mod 4 groups split between its waves; at most three blocks per CU (four: 5 x 4
+  // -4 %, 10 x 2 -0.5 to -0.9 %; two: 10 x 2 -2.5 %); and only where a group has at least 16 steps
+  // (over one wave per group: 5 x 4 +6 to +8 %, 10 x 2 +0.7 to +2.5 %; M = 20 and 48, 8-10 steps
+  // per group, lost 1-4 %).  Interleaved whole groups matter to complex64: contiguous runs of groups per wave cost
   // it 0.6-2 %.
   if constexpr (!PAD && C <= 6) {
     constexpr int rec_bytes = 2 * kWavesPerBlock * (kXfer * 4 + 8);
     const int L = a.F * (a.M / C), wps = kWave / L;
     const bool long_groups = (a.nW + wps - 1) / wps >= 16;
-    for (int bpc = 4; bpc >= 2 && a.flags != nullptr && a.n_cu > 0 && (FMT == FMT_CF32 || long_groups); --bpc) {
+    for (int bpc = FMT == FMT_CF16 ? 3 : 4; bpc >= 2 && a.flags != nullptr && a.n_cu > 0 && (FMT == FMT_CF32 || long_groups); --bpc) {
       const int64_t G = std::min<int64_t>((int64_t)a.n_cu * bpc, a.n_groups);
       const int64_t U = FMT == FMT_CF32 ? balanced_share(a.n_groups, G) : 0;
       const int64_t blocks = U > 0 ? (a.n_groups + U - 1) / U : G;
