@@ -71,7 +71,8 @@ def _gather(out, vis, idx):
 
 
 def test_fp32_baseline_and_fp16_form_full_size():
-    """48 stations, 64 channels, 3072 samples, M = 64: complex64 and complex-half storage."""
+    """48 stations, 64 channels, 3072 samples, M = 64: complex64 and complex-half storage; then
+    the same arrays as one window per integration (M = 3072)."""
     import torch
     scene = synth.scene_fp32_baseline(1)
     vis32 = _device_array(scene, "cf32")
@@ -91,6 +92,17 @@ def test_fp32_baseline_and_fp16_form_full_size():
     disagree = (out16["flags"] != out32["flags"]).float().mean().item()
     print("fp16 form", rep_a, rep_t, "flag disagreement vs complex64 run", disagree)
     assert disagree < 0.01          # the paper reports < 1 % between 32-bit and mixed precision
+
+    # one window per integration (M = T = 3072, the long-window kernel), the benchmark's plan
+    plan_long = dict(d=2.2, s_low=0.9, s_high=1.1, gamma=0.03)
+    op_l = oracle.Params(M=3072, **plan_long)
+    out_l32 = _screen(vis32, scene, 3072, "cf32", **plan_long)
+    v32, g32 = _gather(out_l32, vis32, idx)
+    rep_l32 = compare(g32, v32, op_l, TOL_F32, label="M = 3072 complex64")
+    out_l16 = _screen(vis16, scene, 3072, "cf16", **plan_long)
+    v16, g16 = _gather(out_l16, vis16, idx)
+    rep_l16 = compare(g16, v16, op_l, TOL_F32, label="M = 3072 complex half vs oracle on its bytes")
+    print("one window per integration", rep_l32, rep_l16)
 
 
 @pytest.fixture(scope="module")
