@@ -1,14 +1,16 @@
 // screen.hip -- gfx950 kernels of the online energy + polarisation RFI screen
 // (arXiv 2412.14775, Section 2, Tables 1-2).
 //
-// Four kernels share the per-sample and per-window code below (kernel_for picks one):
-//   screen_tiled    time-only windows of M = 2^k <= 4096 samples (the hot path);
-//   screen_windows  windows of M = K S samples x F channels (non-power-of-two M and
-//                   the paper's time x frequency windows), optionally in the
-//                   paper's mixed precision (Tables 3-4);
-//   screen_long     time-only windows of more than half a step, edges anywhere;
-//   screen_wide     time x frequency windows wider than 64 lanes of runs of 8 samples,
-//                   a window over several steps.
+// Five kernels share the per-sample and per-window code below (kernel_for picks one):
+//   screen_tiled       time-only windows of M = 2^k <= 4096 samples (the hot path);
+//   screen_windows     windows of M = K S samples x F channels (non-power-of-two M and
+//                      the paper's time x frequency windows), optionally in the
+//                      paper's mixed precision (Tables 3-4);
+//   screen_long        time-only windows of more than half a step, edges anywhere;
+//   screen_wide        time x frequency windows wider than 64 lanes of runs of 8
+//                      samples, a window over several steps of one channel each;
+//   screen_wide_pairs  the same over four channels whose runs fit 32 lanes, two
+//                      channels per step.
 //
 // screen_tiled, one pass over the visibilities, bound by HBM bandwidth:
 //   * each wave owns one stream (baseline, channel) or a window-aligned segment
@@ -32,7 +34,8 @@
 //   * at the end of the stream one cross-lane reduction gives the masked sum
 //     and the count of clean samples: average = sum / count, weight = count / T.
 // No atomics: every reduction has a fixed order, so results are bitwise
-// reproducible run to run.
+// reproducible run to run (the same plan, shape and device: a persistent launch that
+// splits a channel group between two waves adds their partial sums in its own order).
 
 #include <algorithm>
 
