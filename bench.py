@@ -178,7 +178,7 @@ def flag_disagreement(a: np.ndarray, b: np.ndarray) -> dict:
 
 # ----------------------------------------------------------------------------- GPU
 
-SETTLE_MS = 30.0                    # GPU time of a form's launches before its timed launches
+SETTLE_MS = 50.0                    # GPU time of a form's launches before its timed launches
 
 
 SETTLE_LOG: dict = {}               # extra warm-up launches per timed form
@@ -188,9 +188,9 @@ def time_form(plan, vis, outs, stream, steps, warmup, key):
     """Warm up, then time `steps` screens with HIP events on the launch stream.
 
     Warm-up is `warmup` launches and then, untimed as well, as many more as it takes for the
-    form's launches to have run SETTLE_MS of GPU time: the first few milliseconds of a form
-    after a switch (other kernels, host work, a fresh array) run up to twice as slow while the
-    GPU's clocks settle (profiles/screen_fp32_baseline.md, launch-to-launch spread).  The
+    form's launches to have run SETTLE_MS of GPU time: the first 20-30 ms of a form after a
+    switch (other kernels, host work, a fresh array) run up to twice as slow while the GPU's
+    clocks settle (profiles/screen_fp32_baseline.md, launch-to-launch spread).  The
     count of those extra launches is logged in SETTLE_LOG under ``key``."""
     import torch
     stream.wait_stream(torch.cuda.current_stream())              # inputs written on torch's stream
