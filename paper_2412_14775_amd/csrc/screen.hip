@@ -334,7 +334,8 @@ constexpr int kXfer = 4 * 8 + 8;  // per-wave LDS record: sums of up to 4 channe
 template <int F>
 __device__ __forceinline__ void finish_stream(const ScreenArgs &a, StreamAcc<F> &acc, int64_t group,
                                               int seg, bool active, int wave, int lane,
-                                              float (*xfer)[kXfer]) {
+                                              float (*xfer)[kXfer], float *lds_out = nullptr,
+                                              int64_t lds_first = 0) {
 #pragma unroll
   for (int f = 0; f < F; ++f)
 #pragma unroll
@@ -382,6 +383,14 @@ __device__ __forceinline__ void finish_stream(const ScreenArgs &a, StreamAcc<F> 
   }
   if (!active || seg != 0 || lane != 0) return;
   const float inv = acc.kept > 0.0f ? 1.0f / acc.kept : 0.0f;
+  if (F == 1 && lds_out != nullptr) {
+    float *o = lds_out + (group - lds_first) * 9;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = acc.sum[0][k] * inv;
+    o[8] = acc.kept * a.invT;
+    if (a.state != nullptr && acc.mom.n > 0u) state_merge(a.state + group, acc.mom);
+    return;
+  }
 #pragma unroll
   for (int f = 0; f < F; ++f) {
     const int64_t stream = group * F + f;
@@ -395,11 +404,12 @@ __device__ __forceinline__ void finish_stream(const ScreenArgs &a, StreamAcc<F> 
 
 // The tiled kernel, for power-of-two window lengths M = 2^LOG2M.  One wave per stream
 // segment; or, PERSIST, block b screens the whole streams [b U, (b + 1) U) (wave w every
-// fourth of them from b U + w) and keeps their flags in LDS until the last is done, then
-// writes them in one pass: flag bytes written back to HBM while the reads stream cost
-// many times their size, written after them hardly anything.
+// fourth of them from b U + w) and keeps their flags, averages and weights in LDS until the
+// last is done, then writes them in one pass: bytes written back to HBM while the reads
+// stream cost many times their size, written after them hardly anything (the averages and
+// weights, 36 bytes a stream, +0.8-1.1 % held back).
 template <int FMT, int LOG2M, bool PERSIST>
-__global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a, int U) {
+__global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a, int U, int hold_avg) {
   constexpr int K = FMT == FMT_CF32 ? 4 : 8;    // samples per lane per step
   constexpr int SB = FMT == FMT_CF32 ? 32 : 16; // bytes per sample
   constexpr int SPI = kWave * K;                // samples per step
@@ -485,7 +495,9 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a, int U
         }
       }
     }
-    finish_stream<1>(a, acc, stream, seg, active, wave, lane, xfer);
+    finish_stream<1>(a, acc, stream, seg, active, wave, lane, xfer,
+                     PERSIST && hold_avg ? reinterpret_cast<float *>(block_flags + ((U * a.nW + 15) & ~15)) : nullptr,
+                     first);
     if (!PERSIST) break;
   }
   if constexpr (PERSIST) {
@@ -493,6 +505,14 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a, int U
     if (a.flags != nullptr) {
       const int64_t base = first * a.nW, n = (last - first) * a.nW;
       for (int64_t i = threadIdx.x; i < n; i += kBlock) a.flags[base + i] = block_flags[i];
+    }
+    const float *bo = reinterpret_cast<const float *>(block_flags + ((U * a.nW + 15) & ~15));
+    for (int64_t i = threadIdx.x; hold_avg && i < last - first; i += kBlock) {
+      const float *o = bo + i * 9;
+      f32x4 *out = reinterpret_cast<f32x4 *>(a.avg + (first + i) * 8);
+      out[0] = f32x4{o[0], o[1], o[2], o[3]};
+      out[1] = f32x4{o[4], o[5], o[6], o[7]};
+      a.weight[first + i] = o[8];
     }
   }
 }
@@ -893,9 +913,23 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a, int
     }
   };
 
-  // Average, weight and adaptive state of a whole group (lane 0's values).
-  auto write_group = [&](int64_t group, const float sums[F][8], float kept, const Moments &mom) {
+  // Average, weight and adaptive state of a whole group (lane 0's values); a persistent block
+  // holds the averages and weights in LDS (hold, 9 floats per channel from group hold_first)
+  // and writes them with its flags.
+  auto write_group = [&](int64_t group, const float sums[F][8], float kept, const Moments &mom,
+                         float *hold = nullptr, int64_t hold_first = 0) {
     const float inv = kept > 0.0f ? 1.0f / kept : 0.0f;
+    if (hold != nullptr) {
+#pragma unroll
+      for (int c = 0; c < F; ++c) {
+        float *o = hold + ((group - hold_first) * F + c) * 9;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[k] = sums[c][k] * inv;
+        o[8] = kept * a.invT;
+      }
+      if (a.state != nullptr && mom.n > 0u) state_merge(a.state + group, mom);
+      return;
+    }
 #pragma unroll
     for (int c = 0; c < F; ++c) {
       const int64_t stream = group * F + c;
@@ -930,6 +964,8 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a, int
     const int64_t last = U > 0 ? min(first + U, a.n_groups) : ((int64_t)blockIdx.x + 1) * a.n_groups / nb;
     if (threadIdx.x < 2 * kWavesPerBlock) rec_group[threadIdx.x] = -1;
     __syncthreads();
+    const int64_t most = U > 0 ? U : (a.n_groups + nb - 1) / nb;   // groups of the largest block
+    float *hold = reinterpret_cast<float *>(block_flags + ((most * a.nW + 15) & ~15));
     const int64_t split0 = first + (last - first) / kWavesPerBlock * kWavesPerBlock;
     for (int64_t group = first + wave; group < split0; group += kWavesPerBlock) {
       StreamAcc<1> acc{};
@@ -937,7 +973,7 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a, int
       float sums[F][8], kept;
       Moments mom;
       reduce_group(acc, sums, kept, mom);
-      if (lane == 0) write_group(group, sums, kept, mom);
+      if (lane == 0) write_group(group, sums, kept, mom, hold, first);
     }
     const int64_t total = (last - split0) * n_steps;
     const int64_t s_end = total * (wave + 1) / kWavesPerBlock;
@@ -953,7 +989,7 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a, int
       Moments mom;
       reduce_group(acc, sums, kept, mom);
       if (st0 == 0 && st1 == n_steps) {         // the whole group in this wave
-        if (lane == 0) write_group(group, sums, kept, mom);
+        if (lane == 0) write_group(group, sums, kept, mom, hold, first);
       } else if (lane == 0) {                   // at most two per wave: its first and its last group
         const int r = 2 * wave + n_rec;
 #pragma unroll
@@ -994,12 +1030,20 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a, int
           mom = moments_merge(mom, b);
           rec_group[q] = -1;
         }
-        write_group(group, sums, kept, mom);
+        write_group(group, sums, kept, mom, hold, first);
       }
     }
+    __syncthreads();
     if (a.flags != nullptr) {
       const int64_t base = first * a.nW, n = (last - first) * a.nW;
       for (int64_t i = threadIdx.x; i < n; i += kBlock) a.flags[base + i] = block_flags[i];
+    }
+    for (int64_t i = threadIdx.x; i < (last - first) * F; i += kBlock) {  // stream first F + i
+      const float *o = hold + i * 9;
+      f32x4 *out = reinterpret_cast<f32x4 *>(a.avg + (first * F + i) * 8);
+      out[0] = f32x4{o[0], o[1], o[2], o[3]};
+      out[1] = f32x4{o[4], o[5], o[6], o[7]};
+      a.weight[first * F + i] = o[8];
     }
   }
 }
@@ -1252,7 +1296,7 @@ constexpr unsigned kTiledCf16Pad[kMaxTiledLog2M + 1] = {0u, 0u, 7680u, 22528u, 2
                                                         7680u, 7680u, 7680u, 22528u, 22528u, 22528u};
 
 // The persistent complex64 tiled launch: three blocks per CU, each holding at most this many
-// flag bytes in LDS (33 KiB static + 19 KiB < 160 KiB / 3).  Complex64 with flags, one
+// bytes of flags, averages and weights in LDS (33 KiB static + 19 KiB < 160 KiB / 3).  Complex64 with flags, one
 // segment per stream: +1 % at M = 64, +4 % at M = 16.  Complex half lost 1-4 % in this form
 // (more registers per loop) and keeps the one-stream-per-wave launch.
 constexpr int kPersistBlocksPerCu = 3;
@@ -1275,11 +1319,13 @@ hipError_t launch_tiled(const ScreenArgs &a, hipStream_t stream) {
     if (a.n_seg == 1 && a.flags != nullptr && a.n_cu > 0) {
       const int64_t G = (int64_t)a.n_cu * kPersistBlocksPerCu;
       const int64_t U = balanced_share(a.n_groups, G);
-      if (U * a.nW <= kPersistFlagBytes) {
+      if (U * a.nW <= kPersistFlagBytes) {   // and the averages too where they fit beside the flags
+        const int hold_avg = ((U * a.nW + 15) & ~15) + U * 36 <= kPersistFlagBytes;
         const int64_t blocks = (a.n_groups + U - 1) / U;
-        const unsigned lds = (unsigned)std::max<int64_t>(U * a.nW, kCf32OccupancyPad);
+        const unsigned lds = (unsigned)std::max<int64_t>(hold_avg ? ((U * a.nW + 15) & ~15) + U * 36 : U * a.nW,
+                                                         kCf32OccupancyPad);
         hipLaunchKernelGGL((screen_tiled<FMT, LOG2M, true>), dim3((unsigned)blocks), dim3(kBlock), lds, stream,
-                           a, (int)U);
+                           a, (int)U, hold_avg);
         return hipGetLastError();
       }
     }
@@ -1287,7 +1333,7 @@ hipError_t launch_tiled(const ScreenArgs &a, hipStream_t stream) {
   const int64_t units = a.n_groups * a.n_seg;
   const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
   const unsigned pad = FMT == FMT_CF32 ? kCf32OccupancyPad : kTiledCf16Pad[LOG2M];
-  hipLaunchKernelGGL((screen_tiled<FMT, LOG2M, false>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a, 0);
+  hipLaunchKernelGGL((screen_tiled<FMT, LOG2M, false>), dim3((unsigned)blocks), dim3(kBlock), pad, stream, a, 0, 0);
   return hipGetLastError();
 }
 
@@ -1423,8 +1469,9 @@ hipError_t launch_windows_k(const ScreenArgs &a, hipStream_t stream) {
       const int64_t blocks = U > 0 ? (a.n_groups + U - 1) / U : G;
       const int64_t most = U > 0 ? U : (a.n_groups + G - 1) / G;   // groups of the largest block
       const int64_t room = 163840 / bpc - 512 - tile_bytes - rec_bytes;
-      if (most * a.nW <= room) {
-        const unsigned lds = (unsigned)std::max<int64_t>(most * a.nW, (int64_t)pad);
+      const int64_t held = ((most * a.nW + 15) & ~15) + most * a.F * 36;   // flags, averages, weights
+      if (held <= room) {
+        const unsigned lds = (unsigned)std::max<int64_t>(held, (int64_t)pad);
         return launch_windows_f<FMT, C, MIXED, PAD, true>(dim3((unsigned)blocks), lds, (int)U, a, stream);
       }
     }
