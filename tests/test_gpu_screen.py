@@ -263,9 +263,12 @@ def test_windows_on_partial_lane_groups(fmt, M, F, C, T):
 
 @pytest.mark.parametrize("fmt", ["cf32", "cf16"])
 @pytest.mark.parametrize("M,F,C,T", [(10, 2, 8, 400), (5, 4, 8, 300), (16, 2, 6, 512), (20, 1, 4, 400),
-                                     (64, 4, 8, 3072)])
+                                     (64, 4, 8, 3072), (10, 2, 8, 3000), (5, 4, 8, 3000)])
 def test_time_frequency_windows(fmt, M, F, C, T):
-    """Windows of M time samples x F adjacent channels (the paper's 10 x 2 and 5 x 4 shapes)."""
+    """Windows of M time samples x F adjacent channels (the paper's 10 x 2 and 5 x 4 shapes).  On
+    3000 samples a channel group has 19 (10 x 2) or 38 (5 x 4) steps and the array only 24 or 12
+    groups, so the persistent launch (complex half too, at 16 or more steps) gives each block one
+    group whose steps its four waves split: four partial records merged per group."""
     vis = scene_vis(3, C, T, seed=31 + M * F, rfi_channels=(1, 2), duty=(50, 12))
     th = thresholds_for(M * F)
     if fmt == "cf32":
