@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(kBlock) screen_tiled(const ScreenArgs a, int U
 
   __shared__ u32x4 tile[kWavesPerBlock][kTilePieces];
   __shared__ float xfer[kWavesPerBlock][kXfer];
-  extern __shared__ __align__(16) uint8_t block_flags[];  // PERSIST: U nW bytes
+  extern __shared__ __align__(16) uint8_t block_flags[];  // PERSIST: U nW flag bytes, then 9 floats a stream
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
@@ -763,6 +763,9 @@ __device__ __forceinline__ void mixed_statistics(const ScreenArgs &a, const floa
 //       raw sum), so every lane reads C samples without tests.  Each lane's load offsets and
 //       tile slots are fixed for the kernel and computed once; the step offset is a scalar.
 //       The channel sums at the end are masked wave sums.
+//   PERSIST = false: one wave per channel group.  PERSIST = true: a block screens a range of
+//       groups and holds their flags, averages and weights in LDS until it is done (the
+//       persistent branch at the end of the kernel).
 template <int FMT, int C, int F, bool MIXED, bool PAD, bool PERSIST>
 __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a, int U) {
   constexpr int SB = FMT == FMT_CF32 ? 32 : 16;
@@ -772,7 +775,7 @@ __global__ void __launch_bounds__(kBlock) screen_windows(const ScreenArgs a, int
   constexpr int CH_SAMPLES = kWave * C / F;     // samples of one channel per step (!PAD)
   static_assert(!(MIXED && PAD), "the paper's mixed precision runs on whole lane groups");
   __shared__ u32x4 tile[kWavesPerBlock][kWave * P];
-  extern __shared__ __align__(16) uint8_t block_flags[];  // PERSIST: U nW bytes
+  extern __shared__ __align__(16) uint8_t block_flags[];  // PERSIST: flag bytes, then 9 floats a stream
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
@@ -1448,8 +1451,8 @@ hipError_t launch_windows_k(const ScreenArgs &a, hipStream_t stream) {
   constexpr unsigned pad = FMT == FMT_CF16 && !PAD && !MIXED && C >= 5 && tile_bytes < kFourBlocksLds
                                ? (unsigned)(kFourBlocksLds - tile_bytes) : 0u;
   // Exact layouts of at most 6 samples per lane with a flag array run persistent, each block's
-  // flags held in LDS until its groups are done, at the most blocks per CU (4, 3, 2) whose flags
-  // fit beside the tile.  Complex64 (the paper's mixed form included): U groups per block, a
+  // flags, averages and weights held in LDS until its groups are done, at the most blocks per CU
+  // (4, 3, 2) whose share fits beside the tile.  Complex64 (the paper's mixed form included): U groups per block, a
   // multiple of the four waves, so each wave screens whole groups (10 x 2 +5.5 %, 5 x 4 +5.1 %,
   // M = 20 +4.5 %, the mixed form +3.4 %, M = 48 +1.1 % over one wave per group; runs of 8 lose
   // 3 %).  Complex half, whose VALU-heavy waves run as fast as their CU lets them, needs the same
