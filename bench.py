@@ -40,7 +40,7 @@ N_STATIONS, N_CHANNELS, N_SAMPLES, BLOCK_M = 48, 64, 3072, 64
 SEED = 1
 # plan thresholds for M = 64 (null quantiles of this generator: SK 2.5 / 97.5 %, DS 95 %)
 PLAN = dict(sk_d=2.2, sk_low=0.656, sk_high=1.487, ds_gamma=0.202)
-CPU_SAMPLE_BASELINES = 600          # baselines (x all 64 channels): about 30 s of oracle CPU work
+CPU_SAMPLE_BASELINES = 1176         # baselines (x all 64 channels): the whole integration, 15-20 s of CPU work on 16 cores
 
 
 def kernel_source_digest() -> str:
@@ -92,8 +92,9 @@ def cpu_baseline(e: np.ndarray) -> dict:
     """FP64 oracle on bounded samples of two workloads, in a process pool over every core this
     process may run on.  Data generation is outside the timed region; only the oracle's
     compute is timed.
-      * the FP32 baseline (48 stations, 64 channels, 3072 samples, M = 64): a seeded sample of
-        CPU_SAMPLE_BASELINES of its 1176 baselines, all channels and samples;
+      * the FP32 baseline (48 stations, 64 channels, 3072 samples, M = 64): CPU_SAMPLE_BASELINES
+        of its 1176 baselines (seeded; all of them by default, the whole integration), all
+        channels and samples;
       * the 64-station mixed case (2080 baselines, 256 channels, M = 64): a seeded 1 % of its
         (baseline, channel) streams (21 baselines, all channels), extrapolated as samples/s."""
     try:
